@@ -1,0 +1,249 @@
+"""Benchmark of the Wilson-Dirac hot path on one MI355X.
+
+Workload (the dslash benchmark): even/odd Wilson dslash on a 16^3 x 32
+lattice (V = 131072, 65536 output sites per apply), m = -1.4, random SU(3)
+links (su(3) generator width 0.3, re-unitarised), complex Gaussian spinors,
+link storage 18/12/8 reals in FP32 and 18 reals in FP64 (plus FP16 storage).
+
+One step = one even/odd dslash apply (1320 flop per output site).  Steps
+alternate D_oe and D_eo over NSETS independent (U, psi_e, psi_o) sets whose
+total size exceeds 512 MB, so consecutive applies cannot reuse each other's
+data from the 256 MB Infinity Cache: the timed applies stream from HBM.
+The timed loop replays a HIP graph of 2*NSETS applies.
+
+Prints one JSON line.  `value` is GFLOP/s of the headline format; the
+`roofline` object is for the headline dslash kernel (algorithmic bytes per
+launch / average launch time from per-launch HIP events on the launch
+stream); `variants` lists every format; `cpu_baseline` times the FP64 oracle
+on the host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+DIMS = (32, 16, 16, 16)
+M = -1.4
+FLOP_PER_SITE = 1320
+HBM_PEAK_GBS = 8000.0
+ROTATE_BYTES = 600e6
+# (name, spinor prec, link prec, recon); the first entry is the headline
+FORMATS = [("f32-r12", 1, 1, 12), ("f32-r18", 1, 1, 18), ("f32-r8", 1, 1, 8), ("f64-r18", 0, 0, 18),
+           ("f16-r12", 2, 2, 12)]
+SPINOR_BYTES = {0: 192, 1: 96, 2: 52}
+LINK_REAL_BYTES = {0: 8, 1: 4, 2: 2}
+
+def bytes_per_site(sp, lp, recon):
+    """Algorithmic bytes per output site of one even/odd dslash: 8 links
+    (each of the 4V links is read once per pair of parities), the input
+    spinor once, the output spinor once."""
+    return 8 * recon * LINK_REAL_BYTES[lp] + 2 * SPINOR_BYTES[sp]
+
+
+def read_traffic(fmt_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "dslash_16c32_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    from paper_1010_5636_amd.profiling import kernel_hash
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    ent = rec.get("formats", {}).get(fmt_name)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def cpu_baseline(max_seconds=20.0):
+    """The FP64 oracle's even/odd dslash on the host, on as many applies as fit
+    in ~max_seconds (at least 2), with BLAS/OpenMP pools limited to 1 thread."""
+    import synthetic
+    from oracle import dirac
+    from threadpoolctl import threadpool_limits
+    v = int(np.prod(DIMS))
+    with threadpool_limits(1):
+        u = synthetic.gauge_field(DIMS)
+        psi = synthetic.spinor(v // 2)
+        dirac.dslash(u, psi, DIMS, 1)  # warm-up
+        n, t0 = 0, time.perf_counter()
+        while True:
+            psi = dirac.dslash(u, psi, DIMS, (n + 1) % 2)   # even -> odd -> even ...
+            n += 1
+            el = time.perf_counter() - t0
+            if (n >= 2 and el > max_seconds) or n >= 50:
+                break
+    gflops = FLOP_PER_SITE * (v // 2) * n / el / 1e9
+    return {"value": round(gflops, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} even/odd dslash applies of the FP64 numpy oracle on the 16^3x32 lattice "
+                      f"({el:.1f} s, one thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--formats", default="all", help="comma list of format names or 'all'")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm-cache", action="store_true", help="reuse one buffer set (data stays in cache)")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of graph replays")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="also run a device-to-device copy of BYTES bytes (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: multi-GPU runs are not part of this build "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+    import synthetic
+    import paper_1010_5636_amd as ndq
+    from paper_1010_5636_amd.ndq import lib
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    lib()  # fails loudly if libndq.so is missing
+    dev = torch.device("cuda")
+    g = ndq.Geometry(DIMS)
+    vh = g.volume // 2
+    u_canon = torch.from_numpy(synthetic.gauge_field(DIMS)).to(dev)
+    psi_canon = torch.from_numpy(synthetic.spinor(vh)).to(dev)
+
+    fmts = FORMATS if args.formats == "all" else [f for f in FORMATS if f[0] in args.formats.split(",")]
+    results = {}
+    for name, sp, lp, recon in fmts:
+        bps = bytes_per_site(sp, lp, recon)
+        set_bytes = g.gauge_bytes(lp, recon) + 2 * g.spinor_bytes(sp, ndq.EVEN, 1)
+        nsets = 1 if args.warm_cache else max(2, int(np.ceil(ROTATE_BYTES / set_bytes)))
+        sets = []
+        for s in range(nsets):
+            U = ndq.GaugeField.pack(g, u_canon, lp, recon)
+            e = ndq.SpinorField.pack(g, psi_canon * (1.0 + 0.01 * s), sp, ndq.EVEN)
+            o = e.like(parity=ndq.ODD)
+            sets.append((U, e, o))
+        torch.cuda.synchronize()
+
+        def step(k):
+            U, e, o = sets[k % nsets]
+            if (k // nsets) % 2 == 0:
+                ndq.apply_dslash(g, U, e, o)
+            else:
+                ndq.apply_dslash(g, U, o, e)
+
+        for k in range(args.warmup):
+            step(k)
+        torch.cuda.synchronize()
+        # graph of 2*nsets applies (every set once in each direction)
+        gsize = 2 * nsets
+        graph = None
+        if not args.no_graph:
+            graph = torch.cuda.CUDAGraph()
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                with torch.cuda.graph(graph, stream=stream):
+                    for k in range(gsize):
+                        step(k)
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            reps, rem = divmod(args.steps, gsize)
+        else:
+            reps, rem = 0, args.steps
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        t_start.record()
+        for _ in range(reps):
+            graph.replay()
+        for k in range(rem):
+            step(k)
+        t_stop.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        ms_total = t_start.elapsed_time(t_stop)
+        # per-launch kernel time: one event pair around each eager launch
+        nk = min(args.steps, 400)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nk)]
+        torch.cuda.synchronize()
+        for k in range(nk):
+            evs[k][0].record()
+            step(k)
+            evs[k][1].record()
+        torch.cuda.synchronize()
+        kt = np.array([a.elapsed_time(b) for a, b in evs]) * 1e-3  # seconds
+        k_avg = float(kt.mean())
+        gflops = FLOP_PER_SITE * vh * args.steps / (ms_total * 1e-3) / 1e9
+        alg_bytes = bps * vh
+        results[name] = {
+            "gflops": round(gflops, 1),
+            "ms_per_step": ms_total / args.steps,
+            "wall_s": wall,
+            "kernel_us_avg": k_avg * 1e6,
+            "kernel_us_median": float(np.median(kt)) * 1e6,
+            "alg_bytes_per_launch": alg_bytes,
+            "hbm_gbs": alg_bytes / k_avg / 1e9,
+            "kernel_gflops": FLOP_PER_SITE * vh / k_avg / 1e9,
+            "frac_hbm": alg_bytes / k_avg / 1e9 / HBM_PEAK_GBS,
+            "nsets": nsets,
+        }
+        del sets, graph
+        torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        src = torch.empty(args.copy_calibration, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    head = fmts[0][0]
+    hr = results[head]
+    traffic = read_traffic(head)
+    out = {
+        "metric": "Dslash GFLOP/s + HBM GB/s; D_N solves/s mixed vs FP64 at 1e-10 rel resid",
+        "value": hr["gflops"],
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(hr["ms_per_step"], 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if fmts[0][1] != 0 else "f64",
+        "data": "synthetic",
+        "config": {"workload": "even/odd Wilson dslash, 16^3x32, m=-1.4, random SU(3) links (width 0.3), "
+                               f"{head} ({'F16' if fmts[0][1] == 2 else 'F32' if fmts[0][1] == 1 else 'F64'} spinors, "
+                               f"{fmts[0][3]}-real links), HBM-streamed (rotating buffer sets)"
+                               if not args.warm_cache else f"{head}, warm cache",
+                   "dims": list(DIMS), "flop_per_site": FLOP_PER_SITE, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(hr["hbm_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(hr["frac_hbm"], 4), "traffic": traffic,
+                     "kernel": "k_wilson (even/odd dslash)", "alg_bytes_per_launch": hr["alg_bytes_per_launch"],
+                     "kernel_us_avg": round(hr["kernel_us_avg"], 3)},
+        "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in r.items()}
+                     for k, r in results.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

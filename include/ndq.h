@@ -1,0 +1,174 @@
+/*
+ * ndq -- the Neuberger-Dirac hot path on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libndq.so.  Operators follow Walk, Wittig, Dranischnikow, Schoemer,
+ * "Implementation of the Neuberger-Dirac operator on GPUs" (Lattice 2010):
+ *
+ *   D_W phi(x) = (4+m) phi(x) - 1/2 sum_{mu=+-0..+-3} U_mu(x)(1-gamma_mu) phi(x+mu)   (Sec. 2.1, Eq. 1)
+ *   U_{-mu}(x) = U_mu(x-mu)^{-1},  gamma_{-mu} = -gamma_mu                            (Eq. 2)
+ *   Q = gamma5 D_W                                                                     (Eq. 1)
+ *   D_N = (1 + gamma5 sign(Q)) / abar                                                  (Sec. 2.2, Eq. 4)
+ *   sign(Q) ~ X P_n(X^2), X = Q/|Q|, P_n = sum_k c_k T_k                               (Eq. 5, Eq. 6)
+ *   sign(Q) ~ P_+ - P_- + (1 - P_+ - P_-) X P_n(X^2)                                   (Sec. 2.3, Eq. 11)
+ *
+ * Conventions used everywhere (the paper leaves them open):
+ *   - periodic boundaries; dims = {N0, N1, N2, N3}, N0 the time extent, every
+ *     extent even and >= 2; lexicographic site index
+ *     lex = ((x0*N1 + x1)*N2 + x2)*N3 + x3;
+ *   - parity (x0+x1+x2+x3) & 1 (even = 0); within a parity, the site with
+ *     lexicographic index lex has even/odd index lex >> 1;
+ *   - chiral Dirac matrices, gamma5 = diag(1, 1, -1, -1); lattice spacing a = 1;
+ *   - D_N with s = -1 - m (m the Wilson mass of Eq. 1), abar = 1/(1+s), and the
+ *     massive operator D_N^m = (1 - abar mq/2) D_N + mq (the form bounded by Eq. 12).
+ *
+ * Memory and ownership:
+ *   - every device buffer is allocated and owned by the caller (the library
+ *     never allocates device memory); *_bytes() queries give the sizes;
+ *   - "canonical" buffers are complex128 (interleaved re, im doubles) in device
+ *     memory: gauge [V][4 mu][3 row][3 col] in lexicographic order; spinor
+ *     [nrhs][nsites][4 spin][3 colour] with nsites = V (lexicographic order)
+ *     for NDQ_FULL fields and V/2 (even/odd index order) for parity fields;
+ *   - packed fields (ndq_gauge, ndq_spinor) use the library's internal
+ *     structure-of-arrays layout and are opaque to the caller;
+ *   - opaque host handles (ndq_geom, ndq_approx) are created and destroyed by
+ *     the library;
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Apply calls are
+ *     asynchronous on that stream; calls that return scalars to the host
+ *     synchronise it.
+ *
+ * Errors: every call returns NDQ_OK (0) or a negative status.  Argument
+ * checks run on the host before anything is launched.  ndq_last_error()
+ * returns a thread-local message for the last failure.  No C++ exception
+ * crosses this boundary.  A failed HIP call returns NDQ_EHIP.
+ */
+#ifndef NDQ_H
+#define NDQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+enum {
+    NDQ_OK = 0,
+    NDQ_EINVAL = -1,     /* bad argument (NULL pointer, out-of-range value)      */
+    NDQ_EDIMS = -2,      /* lattice extent odd, < 2, or volume too large          */
+    NDQ_EPREC = -3,      /* unsupported precision / reconstruction combination    */
+    NDQ_ENOMEM = -4,     /* caller-provided workspace too small                   */
+    NDQ_ESINGULAR = -5,  /* 8-real link with |a2|^2+|a3|^2 < 1e-12, or nu_k = 0   */
+    NDQ_ENOCONV = -6,    /* iterative method hit its iteration limit              */
+    NDQ_ENAN = -7,       /* NaN or Inf in a norm                                   */
+    NDQ_EHIP = -8        /* a HIP runtime call failed                              */
+};
+
+/* ---- enumerations ------------------------------------------------------- */
+enum { NDQ_F64 = 0, NDQ_F32 = 1, NDQ_F16 = 2 };          /* storage precision  */
+enum { NDQ_EVEN = 0, NDQ_ODD = 1, NDQ_FULL = 2 };        /* spinor site subset */
+enum { NDQ_ZOLOTAREV = 0, NDQ_MINMAX_POLY = 1 };         /* sign approximant   */
+enum { NDQ_LITERAL = 0, NDQ_SANDWICH = 1 };              /* Eq. 11 placement   */
+
+/* ---- geometry ----------------------------------------------------------- */
+typedef struct ndq_geom ndq_geom;
+
+/* Create a host-side geometry for a periodic N0 x N1 x N2 x N3 lattice.
+ * dims: host array of 4 extents, each even and >= 2, volume < 2^30.
+ * On success *out receives a handle the caller releases with ndq_geom_destroy.
+ * Errors: NDQ_EINVAL (NULL), NDQ_EDIMS. */
+int ndq_geom_create(const int32_t dims[4], ndq_geom** out);
+void ndq_geom_destroy(ndq_geom* g);
+int64_t ndq_geom_volume(const ndq_geom* g);
+
+/* Index tables produced on the device by the same index arithmetic the
+ * stencil kernels use (Sec. 2.1: one site per lane, neighbours x +- mu).
+ *   d_nb       int32 [V][8]      lexicographic neighbours: +0,+1,+2,+3,-0,-1,-2,-3
+ *   d_lex_of_eo int32 [2][V/2]   lexicographic index of (parity, eo index)
+ *   d_nb_eo    int32 [2][V/2][8] eo index (in the opposite parity) of each neighbour
+ * Any pointer may be NULL to skip that table.  Asynchronous on `stream`. */
+int ndq_geom_tables(const ndq_geom* g, int32_t* d_nb, int32_t* d_lex_of_eo, int32_t* d_nb_eo,
+                    void* stream);
+
+/* ---- fields ------------------------------------------------------------- */
+/* A packed gauge field: data (device) holds all 4V links in `prec` with
+ * `recon` reals per link: 18 (full matrix), 12 (two columns a, b; the third is
+ * c = (a x b)^*, Sec. 2.1 Eq. 3) or 8 (a2, a3, b1, arg a1, arg c1; the rest
+ * from unitarity, the 8-parameter idea of Sec. 2.1).  F64 links need F64
+ * spinors; F16 links support recon 18 and 12. */
+typedef struct {
+    void* data;
+    int32_t prec;
+    int32_t recon;
+} ndq_gauge;
+
+/* A packed spinor field of nrhs right-hand sides on a site subset
+ * (NDQ_EVEN, NDQ_ODD: V/2 sites; NDQ_FULL: V sites).  F16 fields carry one
+ * F32 scale per site and right-hand side inside `data`. */
+typedef struct {
+    void* data;
+    int32_t prec;
+    int32_t parity;
+    int32_t nrhs;
+} ndq_spinor;
+
+size_t ndq_gauge_bytes(const ndq_geom* g, int prec, int recon);
+size_t ndq_spinor_bytes(const ndq_geom* g, int prec, int parity, int nrhs);
+
+/* Convert a canonical complex128 gauge field (device) to the packed format.
+ * Errors: NDQ_EPREC; NDQ_ESINGULAR (recon 8 and some link has
+ * |a2|^2 + |a3|^2 < 1e-12, e.g. the unit field).  Synchronises `stream` for
+ * recon 8 (to read back the singularity flag); otherwise asynchronous. */
+int ndq_gauge_pack(const ndq_geom* g, const void* d_canon, const ndq_gauge* dst, void* stream);
+
+/* Reconstruct a packed gauge field into canonical complex128 (device). */
+int ndq_gauge_unpack(const ndq_geom* g, const ndq_gauge* src, void* d_canon, void* stream);
+
+/* Canonical complex128 spinor (device) <-> packed spinor.  Asynchronous. */
+int ndq_spinor_pack(const ndq_geom* g, const void* d_canon, const ndq_spinor* dst, void* stream);
+int ndq_spinor_unpack(const ndq_geom* g, const ndq_spinor* src, void* d_canon, void* stream);
+
+/* ---- operators ---------------------------------------------------------- */
+/* out = Q in = gamma5 D_W in (Eq. 1) on NDQ_FULL fields; in != out.
+ * Arithmetic in FP64 for F64 fields, FP32 otherwise.  Asynchronous. */
+int ndq_apply_Q(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in,
+                const ndq_spinor* out, void* stream);
+
+/* Even/odd hopping block: out_p = H_{p,1-p} in, where D_W = (4+m) - H/2 and
+ * H psi(x) = sum_{mu=+-0..+-3} U_mu(x)(1-gamma_mu) psi(x+mu) (Eq. 1, Eq. 2).
+ * `in` has parity 1-p, `out` parity p (both NDQ_EVEN/NDQ_ODD); 1320 flop per
+ * output site by the usual convention.  Asynchronous. */
+int ndq_apply_dslash(const ndq_geom* g, const ndq_gauge* U, const ndq_spinor* in,
+                     const ndq_spinor* out, void* stream);
+
+/* Even-site gamma5-Hermitian Schur complement
+ *   Qhat_ee = gamma5 [ (4+m) - H_eo H_oe / (4 (4+m)) ],
+ * using tmp (an NDQ_ODD field of the same precision) as scratch. */
+int ndq_apply_Qhat_ee(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in,
+                      const ndq_spinor* out, const ndq_spinor* tmp, void* stream);
+
+/* ---- launch tuning ------------------------------------------------------ */
+/* Launch shape of the stencil kernels: `block` = 64, 128 or 256 lanes with one
+ * lane per output site, or 0 for the direction-split form (4 wavefronts per 64
+ * sites, one per direction mu, combined in LDS; more wavefronts in flight on
+ * small lattices); `xcd_remap` remaps workgroups so that each of the 8 XCDs
+ * works on one contiguous range of sites (neighbour re-reads then stay in that
+ * XCD's L2).  Process-wide; not thread-safe against concurrent launches.
+ * Errors: NDQ_EINVAL. */
+int ndq_set_launch(int block, int xcd_remap);
+
+/* The same for one storage format only (spinor precision, link precision,
+ * recon); the autotuner records its choice per format this way. */
+int ndq_set_launch_for(int sprec, int lprec, int recon, int block, int xcd_remap);
+
+/* ---- diagnostics -------------------------------------------------------- */
+const char* ndq_last_error(void);
+const char* ndq_status_string(int status);
+/* Library version string, e.g. "ndq 0.1 gfx950". */
+const char* ndq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NDQ_H */

@@ -1,0 +1,8 @@
+"""MI355X-native hot path of the Neuberger-Dirac operator (HIP kernels behind a C ABI).
+
+The compute lives in ``libndq.so`` (built from ``csrc/`` by ``build.py``);
+``ndq`` is its ctypes binding.
+"""
+from . import ndq  # noqa: F401
+from .ndq import (F16, F32, F64, EVEN, ODD, FULL, GaugeField, Geometry, NdqError,  # noqa: F401
+                  SpinorField, apply_dslash, apply_Q, apply_Qhat_ee)

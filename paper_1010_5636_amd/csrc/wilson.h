@@ -1,0 +1,43 @@
+// Launch interface of the Wilson stencil kernel (see wilson.hip).
+#pragma once
+
+#include <string.h>
+
+#include "ndq_internal.h"
+
+namespace ndq {
+
+struct WilsonArgs {
+    GeomK g;
+    int p0;                    // parity of the output sites of grid row y = 0
+    const char* links;
+    SpinorView in[2];          // stencil input (parity 1 - p) per grid row
+    SpinorView out[2];
+    SpinorView self[2];        // same-site term (parity p)
+    int has_self;
+    double a_self, b_hop;
+    int gamma5;
+    Coef c0;
+    Coef cv[3];
+    SpinorView v[3][2];
+    int nv;
+    double* partials;          // per-block |out|^2 partial sums (nullptr: none)
+    int xcd_remap;
+};
+
+// Launch shape of the stencil: block = 64/128/256 lanes with one lane per
+// site, or 0 for the direction-split form; xcd_remap as in ndq_set_launch.
+struct Tuning {
+    int block = 0;
+    int xcd_remap = 1;
+};
+// Per storage format (spinor precision, link precision, recon index 0/1/2 for
+// 18/12/8); set by ndq_set_launch / ndq_set_launch_for (the autotuner).
+Tuning& tuning(int sprec, int lprec, int recon);
+inline int recon_index(int recon) { return recon == 18 ? 0 : recon == 12 ? 1 : 2; }
+
+WilsonArgs wilson_args(const ndq_geom* g, const ndq_gauge* U, int sprec);
+int wilson_blocks(const ndq_geom* g, int block, int ny);
+hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& a, int ny, int block, hipStream_t st);
+
+}  // namespace ndq

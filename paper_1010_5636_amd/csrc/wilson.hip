@@ -1,0 +1,473 @@
+// The Wilson-Dirac stencil (Sec. 2.1, Eq. 1 and Eq. 2) for gfx950.
+//
+// One lane per output site (the paper's one-thread-per-site gather, no
+// inter-lane communication).  Per direction the neighbour spinor is projected
+// onto the two-spin half spinor of (1 -+ gamma_mu), the link (decoded from
+// 18/12/8 stored reals in registers) multiplies the two colour vectors, and
+// the lower spin components are rebuilt by the fixed spin map of the chiral
+// representation.  Accumulation is in registers; the epilogue forms
+//
+//   t   = G5? [ a * self + b * (H in) ]
+//   out = c0 * t + c1 * v1 + c2 * v2 + c3 * v3        (c_k may be device scalars)
+//
+// and optionally adds |out|^2 (FP64) into per-block partial sums.
+// Chiral basis: gamma_mu = [[0, A_mu], [A_mu^H, 0]], A_0 = -1, A_k = -i sigma_k,
+// so (1 - gamma_mu) psi = (h, -A^H h) with h = psi_up - A psi_dn, and
+// (1 + gamma_mu) psi = (g, A^H g) with g = psi_up + A psi_dn.
+#include "wilson.h"
+
+using namespace ndq;
+
+namespace {
+
+// spin s, colour c -> component index 3*s + c
+template <int MU, typename R>
+__device__ __forceinline__ void hop_fwd(const C<R> s[12], const C<R> u[3][3], C<R> acc[12]) {
+    C<R> h0[3], h1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if constexpr (MU == 0) {
+            h0[c] = cadd(s[c], s[6 + c]);
+            h1[c] = cadd(s[3 + c], s[9 + c]);
+        } else if constexpr (MU == 1) {
+            h0[c] = cadd(s[c], cmuli(s[9 + c]));
+            h1[c] = cadd(s[3 + c], cmuli(s[6 + c]));
+        } else if constexpr (MU == 2) {
+            h0[c] = cadd(s[c], s[9 + c]);
+            h1[c] = csub(s[3 + c], s[6 + c]);
+        } else {
+            h0[c] = cadd(s[c], cmuli(s[6 + c]));
+            h1[c] = csub(s[3 + c], cmuli(s[9 + c]));
+        }
+    }
+    C<R> w0[3], w1[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        w0[r] = cmul(u[r][0], h0[0]);
+        w1[r] = cmul(u[r][0], h1[0]);
+        w0[r] = cfma(w0[r], u[r][1], h0[1]);
+        w1[r] = cfma(w1[r], u[r][1], h1[1]);
+        w0[r] = cfma(w0[r], u[r][2], h0[2]);
+        w1[r] = cfma(w1[r], u[r][2], h1[2]);
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        acc[r] = cadd(acc[r], w0[r]);
+        acc[3 + r] = cadd(acc[3 + r], w1[r]);
+        if constexpr (MU == 0) {
+            acc[6 + r] = cadd(acc[6 + r], w0[r]);
+            acc[9 + r] = cadd(acc[9 + r], w1[r]);
+        } else if constexpr (MU == 1) {
+            acc[6 + r] = cadd(acc[6 + r], cmulmi(w1[r]));
+            acc[9 + r] = cadd(acc[9 + r], cmulmi(w0[r]));
+        } else if constexpr (MU == 2) {
+            acc[6 + r] = csub(acc[6 + r], w1[r]);
+            acc[9 + r] = cadd(acc[9 + r], w0[r]);
+        } else {
+            acc[6 + r] = cadd(acc[6 + r], cmulmi(w0[r]));
+            acc[9 + r] = cadd(acc[9 + r], cmuli(w1[r]));
+        }
+    }
+}
+
+template <int MU, typename R>
+__device__ __forceinline__ void hop_bwd(const C<R> s[12], const C<R> u[3][3], C<R> acc[12]) {
+    C<R> g0[3], g1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if constexpr (MU == 0) {
+            g0[c] = csub(s[c], s[6 + c]);
+            g1[c] = csub(s[3 + c], s[9 + c]);
+        } else if constexpr (MU == 1) {
+            g0[c] = csub(s[c], cmuli(s[9 + c]));
+            g1[c] = csub(s[3 + c], cmuli(s[6 + c]));
+        } else if constexpr (MU == 2) {
+            g0[c] = csub(s[c], s[9 + c]);
+            g1[c] = cadd(s[3 + c], s[6 + c]);
+        } else {
+            g0[c] = csub(s[c], cmuli(s[6 + c]));
+            g1[c] = cadd(s[3 + c], cmuli(s[9 + c]));
+        }
+    }
+    // w = U^H g
+    C<R> w0[3], w1[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        w0[r] = cmulc(u[0][r], g0[0]);
+        w1[r] = cmulc(u[0][r], g1[0]);
+        w0[r] = cfmac(w0[r], u[1][r], g0[1]);
+        w1[r] = cfmac(w1[r], u[1][r], g1[1]);
+        w0[r] = cfmac(w0[r], u[2][r], g0[2]);
+        w1[r] = cfmac(w1[r], u[2][r], g1[2]);
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        acc[r] = cadd(acc[r], w0[r]);
+        acc[3 + r] = cadd(acc[3 + r], w1[r]);
+        if constexpr (MU == 0) {
+            acc[6 + r] = csub(acc[6 + r], w0[r]);
+            acc[9 + r] = csub(acc[9 + r], w1[r]);
+        } else if constexpr (MU == 1) {
+            acc[6 + r] = cadd(acc[6 + r], cmuli(w1[r]));
+            acc[9 + r] = cadd(acc[9 + r], cmuli(w0[r]));
+        } else if constexpr (MU == 2) {
+            acc[6 + r] = cadd(acc[6 + r], w1[r]);
+            acc[9 + r] = csub(acc[9 + r], w0[r]);
+        } else {
+            acc[6 + r] = cadd(acc[6 + r], cmuli(w0[r]));
+            acc[9 + r] = cadd(acc[9 + r], cmulmi(w1[r]));
+        }
+    }
+}
+
+template <int SP, int LP, int RECON, int MU>
+__device__ __forceinline__ void hop_pair(const WilsonArgs& a, int p, int32_t i, const int32_t nb[8],
+                                         const SpinorView& vin, C<typename SpinorIO<SP>::R> acc[12]) {
+    using R = typename SpinorIO<SP>::R;
+    C<R> s[12];
+    C<R> u[3][3];
+    SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[MU], s);
+    link_load<LP, RECON>(a.links, a.g.vh, p * 4 + MU, i, u);
+    hop_fwd<MU>(s, u, acc);
+    SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[4 + MU], s);
+    link_load<LP, RECON>(a.links, a.g.vh, (1 - p) * 4 + MU, nb[4 + MU], u);
+    hop_bwd<MU>(s, u, acc);
+}
+
+__device__ __forceinline__ double coef(const Coef& c) { return c.d ? c.f * (*c.d) : c.f; }
+
+// Block index remap that gives each of the 8 XCDs (workgroups dispatched
+// round-robin, linear id mod 8) one contiguous range of tiles, so that
+// neighbour re-reads stay in that XCD's L2.
+__device__ __forceinline__ unsigned xcd_remap(unsigned lin, unsigned total) {
+    const unsigned x = lin & 7u;
+    const unsigned q = total >> 3, r = total & 7u;
+    const unsigned start = x * q + (x < r ? x : r);
+    return start + (lin >> 3);
+}
+
+template <int SP, int LP, int RECON, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_wilson(WilsonArgs a) {
+    using R = typename SpinorIO<SP>::R;
+    __shared__ double red_lds[BLOCK / 64];
+    unsigned lin = blockIdx.y * gridDim.x + blockIdx.x;
+    if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x * gridDim.y);
+    const int y = (int)(lin / gridDim.x);
+    const int32_t i = (int32_t)(lin - (unsigned)y * gridDim.x) * BLOCK + threadIdx.x;
+    const int p = a.p0 + y;
+    double red = 0.0;
+    if (i < a.g.vh) {
+        const SiteCoord x = eo_coords(a.g, p, i);
+        int32_t nb[8];
+        eo_neighbours(a.g, i, x, nb);
+        C<R> acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+        const SpinorView& vin = a.in[y];
+        hop_pair<SP, LP, RECON, 0>(a, p, i, nb, vin, acc);
+        hop_pair<SP, LP, RECON, 1>(a, p, i, nb, vin, acc);
+        hop_pair<SP, LP, RECON, 2>(a, p, i, nb, vin, acc);
+        hop_pair<SP, LP, RECON, 3>(a, p, i, nb, vin, acc);
+
+        const R b = (R)a.b_hop;
+        if (a.has_self) {
+            C<R> sf[12];
+            SpinorIO<SP>::load(a.self[y], (int64_t)a.self[y].site0 + i, sf);
+            const R as = (R)a.a_self;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = {as * sf[k].r + b * acc[k].r, as * sf[k].i + b * acc[k].i};
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = cscale(b, acc[k]);
+        }
+        if (a.gamma5) {
+#pragma unroll
+            for (int k = 6; k < 12; ++k) acc[k] = cneg(acc[k]);
+        }
+        const R c0 = (R)coef(a.c0);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = cscale(c0, acc[k]);
+        for (int j = 0; j < a.nv; ++j) {
+            C<R> vv[12];
+            SpinorIO<SP>::load(a.v[j][y], (int64_t)a.v[j][y].site0 + i, vv);
+            const R cj = (R)coef(a.cv[j]);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = {acc[k].r + cj * vv[k].r, acc[k].i + cj * vv[k].i};
+        }
+        SpinorIO<SP>::store(a.out[y], (int64_t)a.out[y].site0 + i, acc);
+        if (a.partials) {
+            if constexpr (SP == P16) {
+                // norm of what was stored (after F16 rounding)
+                SpinorIO<SP>::load(a.out[y], (int64_t)a.out[y].site0 + i, acc);
+            }
+#pragma unroll
+            for (int k = 0; k < 12; ++k) red += (double)acc[k].r * acc[k].r + (double)acc[k].i * acc[k].i;
+        }
+    }
+    if (a.partials) {
+        const double s = block_sum(red, red_lds);
+        if (threadIdx.x == 0) a.partials[lin] = s;
+    }
+}
+
+// Direction-split variant for small lattices, where one lane per site leaves
+// most SIMDs with a single wavefront: a workgroup of 4 wavefronts covers 64
+// sites and wavefront w computes the two hops +-mu with mu = w (the direction is
+// uniform per wavefront, so there is no divergence).  The four partial sums
+// meet in LDS and are added in a fixed order; wavefront w then finishes spin
+// component w of the 64 outputs.  For F16 outputs wavefront 0 finishes the
+// whole spinor, because the per-site scale needs all 24 reals.
+template <int SP, int LP, int RECON>
+__global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
+    using R = typename SpinorIO<SP>::R;
+    __shared__ C<R> part[4][12][64];
+    __shared__ double red_lds[4];
+    unsigned lin = blockIdx.y * gridDim.x + blockIdx.x;
+    if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x * gridDim.y);
+    const int y = (int)(lin / gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int32_t i = (int32_t)(lin - (unsigned)y * gridDim.x) * 64 + lane;
+    const int p = a.p0 + y;
+    const bool active = i < a.g.vh;
+    if (active) {
+        const SiteCoord x = eo_coords(a.g, p, i);
+        int32_t nb[8];
+        eo_neighbours(a.g, i, x, nb);
+        C<R> acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+        const SpinorView& vin = a.in[y];
+        switch (w) {
+            case 0: hop_pair<SP, LP, RECON, 0>(a, p, i, nb, vin, acc); break;
+            case 1: hop_pair<SP, LP, RECON, 1>(a, p, i, nb, vin, acc); break;
+            case 2: hop_pair<SP, LP, RECON, 2>(a, p, i, nb, vin, acc); break;
+            default: hop_pair<SP, LP, RECON, 3>(a, p, i, nb, vin, acc); break;
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) part[w][k][lane] = acc[k];
+    }
+    __syncthreads();
+    double red = 0.0;
+    if (active) {
+        const R b = (R)a.b_hop;
+        const R as = (R)a.a_self;
+        const R c0 = (R)coef(a.c0);
+        if constexpr (SP == P16) {
+            if (w == 0) {
+                C<R> t[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    t[k] = cadd(cadd(part[0][k][lane], part[1][k][lane]), cadd(part[2][k][lane], part[3][k][lane]));
+                if (a.has_self) {
+                    C<R> sf[12];
+                    SpinorIO<SP>::load(a.self[y], (int64_t)a.self[y].site0 + i, sf);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) t[k] = {as * sf[k].r + b * t[k].r, as * sf[k].i + b * t[k].i};
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) t[k] = cscale(b, t[k]);
+                }
+                if (a.gamma5) {
+#pragma unroll
+                    for (int k = 6; k < 12; ++k) t[k] = cneg(t[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < 12; ++k) t[k] = cscale(c0, t[k]);
+                for (int j = 0; j < a.nv; ++j) {
+                    C<R> vv[12];
+                    SpinorIO<SP>::load(a.v[j][y], (int64_t)a.v[j][y].site0 + i, vv);
+                    const R cj = (R)coef(a.cv[j]);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) t[k] = {t[k].r + cj * vv[k].r, t[k].i + cj * vv[k].i};
+                }
+                SpinorIO<SP>::store(a.out[y], (int64_t)a.out[y].site0 + i, t);
+                if (a.partials) {
+                    SpinorIO<SP>::load(a.out[y], (int64_t)a.out[y].site0 + i, t);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) red += (double)t[k].r * t[k].r + (double)t[k].i * t[k].i;
+                }
+            }
+        } else {
+            const int64_t so = (int64_t)a.out[y].site0 + i;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int c = 3 * w + k;
+                C<R> t = cadd(cadd(part[0][c][lane], part[1][c][lane]), cadd(part[2][c][lane], part[3][c][lane]));
+                if (a.has_self) {
+                    const C<R> sf = SpinorIO<SP>::load_comp(a.self[y], (int64_t)a.self[y].site0 + i, c);
+                    t = {as * sf.r + b * t.r, as * sf.i + b * t.i};
+                } else {
+                    t = cscale(b, t);
+                }
+                if (a.gamma5 && w >= 2) t = cneg(t);
+                t = cscale(c0, t);
+                for (int j = 0; j < a.nv; ++j) {
+                    const C<R> vv = SpinorIO<SP>::load_comp(a.v[j][y], (int64_t)a.v[j][y].site0 + i, c);
+                    const R cj = (R)coef(a.cv[j]);
+                    t = {t.r + cj * vv.r, t.i + cj * vv.i};
+                }
+                SpinorIO<SP>::store_comp(a.out[y], so, c, t);
+                red += (double)t.r * t.r + (double)t.i * t.i;
+            }
+        }
+    }
+    if (a.partials) {
+        const double s = block_sum(red, red_lds);
+        if (threadIdx.x == 0) a.partials[lin] = s;
+    }
+}
+
+template <int SP, int LP, int RECON>
+hipError_t launch_fmt(const WilsonArgs& a, int ny, int block, hipStream_t st) {
+    if (block == 0) {
+        // direction split: 64 sites per workgroup of 4 wavefronts
+        const dim3 grid((unsigned)((a.g.vh + 63) / 64), ny);
+        hipLaunchKernelGGL((k_wilson_dirsplit<SP, LP, RECON>), grid, dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
+    const unsigned nbx = (unsigned)((a.g.vh + block - 1) / block);
+    const dim3 grid(nbx, ny);
+    switch (block) {
+        case 64: hipLaunchKernelGGL((k_wilson<SP, LP, RECON, 64>), grid, dim3(64), 0, st, a); break;
+        case 128: hipLaunchKernelGGL((k_wilson<SP, LP, RECON, 128>), grid, dim3(128), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_wilson<SP, LP, RECON, 256>), grid, dim3(256), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+namespace ndq {
+
+int wilson_blocks(const ndq_geom* g, int block, int ny) {
+    const int per = block == 0 ? 64 : block;
+    return ((g->vh + per - 1) / per) * ny;
+}
+
+hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& a, int ny, int block, hipStream_t st) {
+    const int key = sprec * 1000 + lprec * 100 + recon;
+    switch (key) {
+        case P64 * 1000 + P64 * 100 + 18: return launch_fmt<P64, P64, 18>(a, ny, block, st);
+        case P64 * 1000 + P64 * 100 + 12: return launch_fmt<P64, P64, 12>(a, ny, block, st);
+        case P64 * 1000 + P64 * 100 + 8: return launch_fmt<P64, P64, 8>(a, ny, block, st);
+        case P32 * 1000 + P32 * 100 + 18: return launch_fmt<P32, P32, 18>(a, ny, block, st);
+        case P32 * 1000 + P32 * 100 + 12: return launch_fmt<P32, P32, 12>(a, ny, block, st);
+        case P32 * 1000 + P32 * 100 + 8: return launch_fmt<P32, P32, 8>(a, ny, block, st);
+        case P32 * 1000 + P16 * 100 + 18: return launch_fmt<P32, P16, 18>(a, ny, block, st);
+        case P32 * 1000 + P16 * 100 + 12: return launch_fmt<P32, P16, 12>(a, ny, block, st);
+        case P16 * 1000 + P32 * 100 + 18: return launch_fmt<P16, P32, 18>(a, ny, block, st);
+        case P16 * 1000 + P32 * 100 + 12: return launch_fmt<P16, P32, 12>(a, ny, block, st);
+        case P16 * 1000 + P32 * 100 + 8: return launch_fmt<P16, P32, 8>(a, ny, block, st);
+        case P16 * 1000 + P16 * 100 + 18: return launch_fmt<P16, P16, 18>(a, ny, block, st);
+        case P16 * 1000 + P16 * 100 + 12: return launch_fmt<P16, P16, 12>(a, ny, block, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+WilsonArgs wilson_args(const ndq_geom* g, const ndq_gauge* U, int sprec) {
+    WilsonArgs a;
+    memset(&a, 0, sizeof(a));
+    a.g = g->k;
+    a.links = static_cast<const char*>(U->data);
+    a.c0 = {1.0, nullptr};
+    a.xcd_remap = tuning(sprec, U->prec, U->recon).xcd_remap;
+    return a;
+}
+
+}  // namespace ndq
+
+extern "C" {
+
+int ndq_apply_Q(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in, const ndq_spinor* out,
+                void* stream) {
+    if (!g) return fail(NDQ_EINVAL, "ndq_apply_Q: NULL geometry");
+    int rc = check_gauge(U);
+    if (!rc) rc = check_spinor(g, in, NDQ_FULL, "ndq_apply_Q in");
+    if (!rc) rc = check_spinor(g, out, NDQ_FULL, "ndq_apply_Q out");
+    if (!rc) rc = check_pair(U, in);
+    if (rc) return rc;
+    if (in->prec != out->prec || in->nrhs != out->nrhs)
+        return fail(NDQ_EINVAL, "ndq_apply_Q: in and out must share precision and nrhs");
+    if (in->data == out->data) return fail(NDQ_EINVAL, "ndq_apply_Q: in and out must not alias");
+    hipStream_t st = as_stream(stream);
+    for (int r = 0; r < in->nrhs; ++r) {
+        WilsonArgs a = wilson_args(g, U, in->prec);
+        a.p0 = 0;
+        for (int p = 0; p < 2; ++p) {
+            a.in[p] = view_of(g, in, 1 - p, r);
+            a.self[p] = view_of(g, in, p, r);
+            a.out[p] = view_of(g, out, p, r);
+        }
+        a.has_self = 1;
+        a.a_self = 4.0 + m;
+        a.b_hop = -0.5;
+        a.gamma5 = 1;
+        NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 2, tuning(in->prec, U->prec, U->recon).block, st));
+    }
+    return NDQ_OK;
+}
+
+int ndq_apply_dslash(const ndq_geom* g, const ndq_gauge* U, const ndq_spinor* in, const ndq_spinor* out,
+                     void* stream) {
+    if (!g) return fail(NDQ_EINVAL, "ndq_apply_dslash: NULL geometry");
+    int rc = check_gauge(U);
+    if (!rc) rc = check_spinor(g, in, -1, "ndq_apply_dslash in");
+    if (!rc) rc = check_spinor(g, out, -1, "ndq_apply_dslash out");
+    if (!rc) rc = check_pair(U, in);
+    if (rc) return rc;
+    if (in->parity == NDQ_FULL || out->parity == NDQ_FULL || in->parity == out->parity)
+        return fail(NDQ_EINVAL, "ndq_apply_dslash: in and out must be opposite parity fields");
+    if (in->prec != out->prec || in->nrhs != out->nrhs)
+        return fail(NDQ_EINVAL, "ndq_apply_dslash: in and out must share precision and nrhs");
+    hipStream_t st = as_stream(stream);
+    const int p = out->parity;
+    for (int r = 0; r < in->nrhs; ++r) {
+        WilsonArgs a = wilson_args(g, U, in->prec);
+        a.p0 = p;
+        a.in[0] = view_of(g, in, 1 - p, r);
+        a.out[0] = view_of(g, out, p, r);
+        a.has_self = 0;
+        a.b_hop = 1.0;
+        a.gamma5 = 0;
+        NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 1, tuning(in->prec, U->prec, U->recon).block, st));
+    }
+    return NDQ_OK;
+}
+
+int ndq_apply_Qhat_ee(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in, const ndq_spinor* out,
+                      const ndq_spinor* tmp, void* stream) {
+    if (!g) return fail(NDQ_EINVAL, "ndq_apply_Qhat_ee: NULL geometry");
+    int rc = check_gauge(U);
+    if (!rc) rc = check_spinor(g, in, NDQ_EVEN, "ndq_apply_Qhat_ee in");
+    if (!rc) rc = check_spinor(g, out, NDQ_EVEN, "ndq_apply_Qhat_ee out");
+    if (!rc) rc = check_spinor(g, tmp, NDQ_ODD, "ndq_apply_Qhat_ee tmp");
+    if (!rc) rc = check_pair(U, in);
+    if (rc) return rc;
+    if (in->prec != out->prec || in->prec != tmp->prec || in->nrhs != out->nrhs || tmp->nrhs < in->nrhs)
+        return fail(NDQ_EINVAL, "ndq_apply_Qhat_ee: fields must share precision and nrhs");
+    if (in->data == out->data) return fail(NDQ_EINVAL, "ndq_apply_Qhat_ee: in and out must not alias");
+    if (4.0 + m == 0.0) return fail(NDQ_ESINGULAR, "ndq_apply_Qhat_ee: 4 + m = 0");
+    hipStream_t st = as_stream(stream);
+    for (int r = 0; r < in->nrhs; ++r) {
+        WilsonArgs a = wilson_args(g, U, in->prec);
+        a.p0 = 1;
+        a.in[0] = view_of(g, in, 0, r);
+        a.out[0] = view_of(g, tmp, 1, r);
+        a.b_hop = 1.0;
+        NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 1, tuning(in->prec, U->prec, U->recon).block, st));
+        WilsonArgs b = wilson_args(g, U, in->prec);
+        b.p0 = 0;
+        b.in[0] = view_of(g, tmp, 1, r);
+        b.self[0] = view_of(g, in, 0, r);
+        b.out[0] = view_of(g, out, 0, r);
+        b.has_self = 1;
+        b.a_self = 4.0 + m;
+        b.b_hop = -1.0 / (4.0 * (4.0 + m));
+        b.gamma5 = 1;
+        NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, b, 1, tuning(in->prec, U->prec, U->recon).block, st));
+    }
+    return NDQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,230 @@
+"""Python binding of libndq (ctypes).
+
+Argument marshalling only: every operation runs in the HIP kernels of
+libndq.so.  PyTorch supplies device memory (uint8 buffers sized by the
+library's *_bytes queries) and the current HIP stream.  Function names follow
+the C entry points without their ``ndq_`` prefix.
+
+Raises ``NdqError`` for any non-zero status and ``RuntimeError`` when the
+library has not been built (no silent fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libndq.so")
+_lib = None
+
+F64, F32, F16 = 0, 1, 2
+EVEN, ODD, FULL = 0, 1, 2
+ZOLOTAREV, MINMAX_POLY = 0, 1
+LITERAL, SANDWICH = 0, 1
+
+STATUS = {0: "NDQ_OK", -1: "NDQ_EINVAL", -2: "NDQ_EDIMS", -3: "NDQ_EPREC", -4: "NDQ_ENOMEM",
+          -5: "NDQ_ESINGULAR", -6: "NDQ_ENOCONV", -7: "NDQ_ENAN", -8: "NDQ_EHIP"}
+
+
+class NdqError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Gauge(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("prec", ctypes.c_int32), ("recon", ctypes.c_int32)]
+
+
+class _Spinor(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("prec", ctypes.c_int32), ("parity", ctypes.c_int32),
+                ("nrhs", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_SIG = {
+    "ndq_last_error": (ctypes.c_char_p, []),
+    "ndq_status_string": (ctypes.c_char_p, [_I]),
+    "ndq_version": (ctypes.c_char_p, []),
+    "ndq_geom_create": (_I, [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_P)]),
+    "ndq_geom_destroy": (None, [_P]),
+    "ndq_geom_volume": (ctypes.c_int64, [_P]),
+    "ndq_geom_tables": (_I, [_P, _P, _P, _P, _P]),
+    "ndq_gauge_bytes": (ctypes.c_size_t, [_P, _I, _I]),
+    "ndq_spinor_bytes": (ctypes.c_size_t, [_P, _I, _I, _I]),
+    "ndq_gauge_pack": (_I, [_P, _P, ctypes.POINTER(_Gauge), _P]),
+    "ndq_gauge_unpack": (_I, [_P, ctypes.POINTER(_Gauge), _P, _P]),
+    "ndq_spinor_pack": (_I, [_P, _P, ctypes.POINTER(_Spinor), _P]),
+    "ndq_spinor_unpack": (_I, [_P, ctypes.POINTER(_Spinor), _P, _P]),
+    "ndq_apply_Q": (_I, [_P, ctypes.POINTER(_Gauge), _D, ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P]),
+    "ndq_apply_dslash": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P]),
+    "ndq_apply_Qhat_ee": (_I, [_P, ctypes.POINTER(_Gauge), _D, ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor),
+                               ctypes.POINTER(_Spinor), _P]),
+    "ndq_set_launch": (_I, [_I, _I]),
+    "ndq_set_launch_for": (_I, [_I, _I, _I, _I, _I]),
+}
+
+
+def lib():
+    """The loaded libndq.so (loads it on first use; raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with paper_1010_5636_amd.build.build()")
+        handle = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in _SIG.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise NdqError(rc, lib().ndq_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def status_string(status: int) -> str:
+    return lib().ndq_status_string(status).decode()
+
+
+def version() -> str:
+    return lib().ndq_version().decode()
+
+
+def set_launch(block: int, xcd_remap: bool = True):
+    """Launch shape for every storage format (block 0 = direction split)."""
+    _check(lib().ndq_set_launch(block, int(bool(xcd_remap))))
+
+
+def set_launch_for(sprec: int, lprec: int, recon: int, block: int, xcd_remap: bool = True):
+    _check(lib().ndq_set_launch_for(sprec, lprec, recon, block, int(bool(xcd_remap))))
+
+
+class Geometry:
+    """Host handle of a periodic N0 x N1 x N2 x N3 lattice (ndq_geom)."""
+
+    def __init__(self, dims):
+        self.dims = tuple(int(d) for d in dims)
+        arr = (ctypes.c_int32 * 4)(*self.dims)
+        h = ctypes.c_void_p()
+        _check(lib().ndq_geom_create(arr, ctypes.byref(h)))
+        self.handle = h
+        self.volume = int(lib().ndq_geom_volume(h))
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.ndq_geom_destroy(self.handle)
+            self.handle = None
+
+    def tables(self, stream=None):
+        """(nb [V,8], lex_of_eo [2,V/2], nb_eo [2,V/2,8]) int32 device tensors."""
+        v = self.volume
+        dev = torch.device("cuda")
+        nb = torch.empty((v, 8), dtype=torch.int32, device=dev)
+        leo = torch.empty((2, v // 2), dtype=torch.int32, device=dev)
+        nbe = torch.empty((2, v // 2, 8), dtype=torch.int32, device=dev)
+        _check(lib().ndq_geom_tables(self.handle, _ptr(nb), _ptr(leo), _ptr(nbe), _stream(stream)))
+        return nb, leo, nbe
+
+    def gauge_bytes(self, prec: int, recon: int) -> int:
+        return int(lib().ndq_gauge_bytes(self.handle, prec, recon))
+
+    def spinor_bytes(self, prec: int, parity: int, nrhs: int = 1) -> int:
+        return int(lib().ndq_spinor_bytes(self.handle, prec, parity, nrhs))
+
+
+class GaugeField:
+    """A packed gauge field in device memory owned by a torch uint8 buffer."""
+
+    def __init__(self, geom: Geometry, prec: int, recon: int, buffer: torch.Tensor | None = None):
+        nbytes = geom.gauge_bytes(prec, recon)
+        if nbytes == 0:
+            raise NdqError(-3, f"unsupported gauge format prec={prec} recon={recon}")
+        self.geom, self.prec, self.recon = geom, prec, recon
+        self.buf = buffer if buffer is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.desc = _Gauge(self.buf.data_ptr(), prec, recon)
+
+    @classmethod
+    def pack(cls, geom: Geometry, canon: torch.Tensor, prec: int, recon: int, stream=None):
+        canon = _canon(canon, (geom.volume, 4, 3, 3))
+        u = cls(geom, prec, recon)
+        _check(lib().ndq_gauge_pack(geom.handle, _ptr(canon), ctypes.byref(u.desc), _stream(stream)))
+        return u
+
+    def unpack(self, stream=None) -> torch.Tensor:
+        out = torch.empty((self.geom.volume, 4, 3, 3), dtype=torch.complex128, device="cuda")
+        _check(lib().ndq_gauge_unpack(self.geom.handle, ctypes.byref(self.desc), _ptr(out), _stream(stream)))
+        return out
+
+
+class SpinorField:
+    """A packed spinor field (nrhs right-hand sides on EVEN, ODD or FULL sites)."""
+
+    def __init__(self, geom: Geometry, prec: int, parity: int, nrhs: int = 1, buffer: torch.Tensor | None = None):
+        nbytes = geom.spinor_bytes(prec, parity, nrhs)
+        if nbytes == 0:
+            raise NdqError(-1, f"bad spinor format prec={prec} parity={parity} nrhs={nrhs}")
+        self.geom, self.prec, self.parity, self.nrhs = geom, prec, parity, nrhs
+        self.nsites = geom.volume if parity == FULL else geom.volume // 2
+        self.buf = buffer if buffer is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.desc = _Spinor(self.buf.data_ptr(), prec, parity, nrhs)
+
+    @classmethod
+    def pack(cls, geom: Geometry, canon: torch.Tensor, prec: int, parity: int, stream=None):
+        nsites = geom.volume if parity == FULL else geom.volume // 2
+        nrhs = 1 if canon.dim() == 3 else canon.shape[0]
+        canon = _canon(canon, (nrhs, nsites, 4, 3))
+        s = cls(geom, prec, parity, nrhs)
+        _check(lib().ndq_spinor_pack(geom.handle, _ptr(canon), ctypes.byref(s.desc), _stream(stream)))
+        return s
+
+    def unpack(self, stream=None) -> torch.Tensor:
+        out = torch.empty((self.nrhs, self.nsites, 4, 3), dtype=torch.complex128, device="cuda")
+        _check(lib().ndq_spinor_unpack(self.geom.handle, ctypes.byref(self.desc), _ptr(out), _stream(stream)))
+        return out
+
+    def like(self, parity: int | None = None, prec: int | None = None) -> "SpinorField":
+        return SpinorField(self.geom, self.prec if prec is None else prec,
+                           self.parity if parity is None else parity, self.nrhs)
+
+
+def _canon(t: torch.Tensor, shape) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    if t.dtype != torch.complex128:
+        t = t.to(torch.complex128)
+    if t.device.type != "cuda":
+        t = t.to("cuda")
+    t = t.reshape(shape)
+    return t.contiguous()
+
+
+def apply_Q(geom: Geometry, U: GaugeField, m: float, inp: SpinorField, out: SpinorField, stream=None):
+    _check(lib().ndq_apply_Q(geom.handle, ctypes.byref(U.desc), float(m), ctypes.byref(inp.desc),
+                             ctypes.byref(out.desc), _stream(stream)))
+
+
+def apply_dslash(geom: Geometry, U: GaugeField, inp: SpinorField, out: SpinorField, stream=None):
+    _check(lib().ndq_apply_dslash(geom.handle, ctypes.byref(U.desc), ctypes.byref(inp.desc),
+                                  ctypes.byref(out.desc), _stream(stream)))
+
+
+def apply_Qhat_ee(geom: Geometry, U: GaugeField, m: float, inp: SpinorField, out: SpinorField,
+                  tmp: SpinorField, stream=None):
+    _check(lib().ndq_apply_Qhat_ee(geom.handle, ctypes.byref(U.desc), float(m), ctypes.byref(inp.desc),
+                                   ctypes.byref(out.desc), ctypes.byref(tmp.desc), _stream(stream)))

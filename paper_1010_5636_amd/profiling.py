@@ -1,0 +1,144 @@
+"""Summaries of rocprofv3 output for the stencil kernels.
+
+    python -m paper_1010_5636_amd.profiling stats   <trace_dir>  <out.txt>
+    python -m paper_1010_5636_amd.profiling traffic <fetch_dir> <write_dir> <copy_bytes> <out.json>
+
+``stats`` condenses ``*kernel_stats.csv`` (from ``rocprofv3 --kernel-trace
+--stats``) into a short text table.  ``traffic`` reads the per-dispatch
+FETCH_SIZE and WRITE_SIZE counters (KiB, from two ``rocprofv3 --pmc`` runs),
+calibrates them against a plain device-to-device copy of ``copy_bytes`` bytes
+each way recorded in the same runs, and writes the HBM bytes per launch of
+every Wilson stencil instantiation, tagged with the hash of the kernel source.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_1010_5636_amd/csrc/wilson.hip", "paper_1010_5636_amd/csrc/ndq_device.h"]
+_FMT = re.compile(r"k_wilson(_dirsplit)?<(\d+), (\d+), (\d+)")
+_PREC = {0: "f64", 1: "f32", 2: "f16"}
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def format_name(kernel: str):
+    """'f32-r12' style name of a stencil instantiation (spinor prec, recon), or None."""
+    m = _FMT.search(kernel)
+    if not m:
+        return None
+    sp, lp, recon = int(m.group(2)), int(m.group(3)), int(m.group(4))
+    name = f"{_PREC[sp]}-r{recon}"
+    if lp != sp:
+        name += f"-l{_PREC[lp]}"
+    return name
+
+
+def _csvs(d: str, suffix: str):
+    return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+
+
+def kernel_stats(trace_dir: str):
+    rows = []
+    for path in _csvs(trace_dir, "kernel_stats.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                rows.append({"name": r["Name"], "calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
+                             "min_ns": float(r.get("MinNs", 0) or 0), "max_ns": float(r.get("MaxNs", 0) or 0)})
+    return rows
+
+
+def stats_text(trace_dir: str, command: str) -> str:
+    rows = sorted(kernel_stats(trace_dir), key=lambda r: -r["calls"] * r["avg_ns"])
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
+             f"{'format':<14}{'calls':>8}{'avg_us':>10}{'min_us':>10}{'max_us':>10}  kernel"]
+    for r in rows:
+        fmt = format_name(r["name"]) or "-"
+        lines.append(f"{fmt:<14}{r['calls']:>8}{r['avg_ns'] / 1e3:>10.3f}{r['min_ns'] / 1e3:>10.3f}"
+                     f"{r['max_ns'] / 1e3:>10.3f}  {r['name'][:110]}")
+    return "\n".join(lines) + "\n"
+
+
+def counters(pmc_dir: str, counter: str):
+    """{kernel name: [per-dispatch value]} for one counter."""
+    out = {}
+    for path in _csvs(pmc_dir, "counter_collection.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") != counter:
+                    continue
+                out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def _copy_reading(vals: dict, copy_bytes: int):
+    """Counter reading (KiB) of the calibration copy: the largest-reading
+    dispatch of a runtime copy kernel."""
+    best = None
+    for name, v in vals.items():
+        if "copy" in name.lower() or "Copy" in name:
+            m = max(v)
+            best = m if best is None else max(best, m)
+    return best
+
+
+def traffic(fetch_dir: str, write_dir: str, copy_bytes: int, command: str):
+    fetch = counters(fetch_dir, "FETCH_SIZE")
+    write = counters(write_dir, "WRITE_SIZE")
+    cf = _copy_reading(fetch, copy_bytes)
+    cw = _copy_reading(write, copy_bytes)
+    if not cf or not cw:
+        raise RuntimeError("calibration copy kernel not found in the counter output")
+    sf = copy_bytes / cf   # bytes per counter unit
+    sw = copy_bytes / cw
+    rec = {"kernel_hash": kernel_hash(), "command": command, "copy_bytes": copy_bytes,
+           "fetch_scale_bytes_per_unit": sf, "write_scale_bytes_per_unit": sw, "formats": {}}
+    for name, v in fetch.items():
+        fmt = format_name(name)
+        if fmt is None:
+            continue
+        w = write.get(name)
+        if not w:
+            continue
+        fb = sf * sorted(v)[len(v) // 2]
+        wb = sw * sorted(w)[len(w) // 2]
+        rec["formats"].setdefault(fmt, {})
+        rec["formats"][fmt].update({"kernel": name[:120], "fetch_bytes_per_launch": fb,
+                                    "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
+                                    "dispatches": len(v)})
+    return rec
+
+
+def main(argv):
+    if len(argv) >= 3 and argv[0] == "stats":
+        cmd = argv[3] if len(argv) > 3 else ""
+        txt = stats_text(argv[1], cmd)
+        with open(argv[2], "w") as fh:
+            fh.write(txt)
+        print(txt)
+        return 0
+    if len(argv) >= 5 and argv[0] == "traffic":
+        cmd = argv[5] if len(argv) > 5 else ""
+        rec = traffic(argv[1], argv[2], int(argv[3]), cmd)
+        with open(argv[4], "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec, indent=1))
+        return 0
+    print(__doc__)
+    return 2
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))
