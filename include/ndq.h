@@ -147,6 +147,74 @@ int ndq_apply_dslash(const ndq_geom* g, const ndq_gauge* U, const ndq_spinor* in
 int ndq_apply_Qhat_ee(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in,
                       const ndq_spinor* out, const ndq_spinor* tmp, void* stream);
 
+/* ---- sign-function approximants (host) ----------------------------------- */
+typedef struct ndq_approx ndq_approx;
+
+/* Build an approximant of sign(x), x = lambda/|Q|:
+ *   NDQ_MINMAX_POLY: x P(x^2), P = sum_{k=0}^{degree} c_k T_k(z), z = (2y-1-lo)/(1-lo),
+ *     minimising max_{lo<=y<=1} |1 - sqrt(y) P(y)| (Sec. 2.2, Eq. 5 and Eq. 6; lo = eps);
+ *     Remez exchange, degree in [0, 2000];
+ *   NDQ_ZOLOTAREV: x sum_{l=1}^{degree} beta_l / (x^2 + sigma_l), the optimal rational
+ *     approximation on lo <= |x| <= 1 (lo = k), degree (poles) in [1, 32].
+ * Host only (no GPU needed).  Errors: NDQ_EINVAL, NDQ_ENOCONV. */
+int ndq_approx_create(int kind, double lo, int degree, ndq_approx** out);
+/* Wrap caller-supplied coefficients: a = sigma[n] and b = beta[n] (Zolotarev) or
+ * a = c[n+1] (polynomial); `delta` is recorded as given. */
+int ndq_approx_from_coeffs(int kind, int n, const double* a, const double* b, double lo, double delta,
+                           ndq_approx** out);
+/* kind, n (poles or degree), lo, and delta = max approximation error on the interval. */
+int ndq_approx_info(const ndq_approx* ap, int* kind, int* n, double* lo, double* delta);
+/* Copy coefficients to host arrays: a gets sigma[n] or c[n+1]; b gets beta[n] (may be NULL). */
+int ndq_approx_coeffs(const ndq_approx* ap, double* a, double* b);
+void ndq_approx_destroy(ndq_approx* ap);
+
+/* ---- sign(Q) and D_N ------------------------------------------------------ */
+typedef struct {
+    double m;                 /* Wilson mass of Eq. 1; s = -1 - m, abar = 1/(1+s)            */
+    double mq;                /* quark mass of D_N^m                                          */
+    double lam_max;           /* |Q| (or an upper bound) used in X = Q / lam_max              */
+    const ndq_approx* approx; /* approximant of sign on the complement of the low modes      */
+    const void* modes;        /* device: nev packed F64 NDQ_FULL spinors, back to back,
+                                 orthonormal Rayleigh-Ritz vectors u_k (may be NULL if nev=0) */
+    const double* nu;         /* host: the nev eigenvalues nu_k (P Q u_k = nu_k u_k), nonzero */
+    int32_t nev;              /* number of low modes treated exactly, 0..64                   */
+    int32_t form;             /* NDQ_LITERAL (Eq. 11 as printed) or NDQ_SANDWICH              */
+    double tol;               /* rational approximant: multi-shift CG relative residual       */
+    int32_t max_iter;         /* rational approximant: CG iteration limit                     */
+    int32_t check_every;      /* rational approximant: convergence read-back interval (>= 1)  */
+} ndq_overlap_params;
+
+typedef struct {
+    int64_t q_applies;        /* stencil applications                                         */
+    int32_t iterations;       /* CG iterations (rational) or Clenshaw steps (polynomial)      */
+    int32_t outer;            /* outer defect-correction steps (solve)                        */
+    int64_t inner;            /* inner CG iterations summed over outer steps (solve)          */
+    double residual;          /* final relative residual (CG, or true residual for a solve)   */
+    double seconds;           /* host wall time of the call                                   */
+} ndq_stats;
+
+enum { NDQ_OP_SIGN = 0, NDQ_OP_DN = 1, NDQ_OP_SOLVE = 2 };
+
+/* Workspace (device bytes) that ndq_apply_sign / ndq_apply_DN / ndq_solve_DN need
+ * for fields of precision `prec`.  0 on invalid arguments. */
+size_t ndq_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p, int prec, int op);
+
+/* out = sign(Q) in by Eq. 11: with c = U^H in and t = X r(X^2) in (the approximant
+ * evaluated by Clenshaw's recurrence for the polynomial, by multi-shift CG for the
+ * rational form), out = t + U (sign(nu) * c - U^H t); NDQ_SANDWICH applies the
+ * approximant to (1 - P) in instead.  in, out: NDQ_FULL, nrhs 1, same precision
+ * (arithmetic FP64 for F64 fields, FP32 otherwise; projections always FP64).
+ * Synchronises `stream` for the rational approximant (convergence checks).
+ * Errors: NDQ_ENOMEM (workspace), NDQ_ENOCONV (CG limit), NDQ_ENAN, NDQ_ESINGULAR (nu_k = 0). */
+int ndq_apply_sign(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p,
+                   const ndq_spinor* in, const ndq_spinor* out, void* ws, size_t ws_bytes,
+                   ndq_stats* stats, void* stream);
+
+/* out = D_N^m in = (1/abar - mq/2)(in + gamma5 sign(Q) in) + mq in  (Eq. 4, Eq. 12). */
+int ndq_apply_DN(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p,
+                 const ndq_spinor* in, const ndq_spinor* out, void* ws, size_t ws_bytes,
+                 ndq_stats* stats, void* stream);
+
 /* ---- launch tuning ------------------------------------------------------ */
 /* Launch shape of the stencil kernels: `block` = 64, 128 or 256 lanes with one
  * lane per output site, or 0 for the direction-split form (4 wavefronts per 64

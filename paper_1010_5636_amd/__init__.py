@@ -4,5 +4,6 @@ The compute lives in ``libndq.so`` (built from ``csrc/`` by ``build.py``);
 ``ndq`` is its ctypes binding.
 """
 from . import ndq  # noqa: F401
-from .ndq import (F16, F32, F64, EVEN, ODD, FULL, GaugeField, Geometry, NdqError,  # noqa: F401
-                  SpinorField, apply_dslash, apply_Q, apply_Qhat_ee)
+from .ndq import (F16, F32, F64, EVEN, ODD, FULL, LITERAL, SANDWICH, MINMAX_POLY, ZOLOTAREV,  # noqa: F401
+                  Approx, GaugeField, Geometry, NdqError, Overlap, SpinorField, apply_DN, apply_dslash, apply_Q,
+                  apply_Qhat_ee, apply_sign)

@@ -2,7 +2,7 @@
 
     python -m paper_1010_5636_amd.build        # or build() from Python
 
-Every .hip file under csrc/ is compiled separately with hipcc and linked into
+Every .hip and .cpp file under csrc/ is compiled separately with hipcc and linked into
 paper_1010_5636_amd/libndq.so.  Object files go to _build/ at the repository
 root.
 """
@@ -32,11 +32,11 @@ CFLAGS = [
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
 def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
+    obj = os.path.join(BUILD, os.path.splitext(os.path.basename(src))[0] + ".o")
     cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

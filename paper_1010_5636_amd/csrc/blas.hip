@@ -1,0 +1,535 @@
+// Site-local vector kernels of the sign-function and solver layers: linear
+// combinations (with optional gamma5), FP64 reductions in a fixed order,
+// precision conversion, the fused multi-shift CG update with its device-side
+// scalar recurrences, and the low-mode projection (multi-dot and rank-nev
+// update against FP64 eigenvectors).
+//
+// One lane per site; fields are full spinors viewed as V consecutive sites.
+// Reductions: each block writes its partial sums; a single-block kernel adds
+// them in index order, so results do not depend on scheduling.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "ndq_solver.h"
+
+using namespace ndq;
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double coefv(const Coef& c) { return c.d ? c.f * (*c.d) : c.f; }
+
+struct LinArgs {
+    SpinorView out;
+    SpinorView v[4];
+    Coef c[4];
+    int g5[4];
+    int nv;
+    int32_t nsites;
+    double* partials;
+};
+
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_lincomb(LinArgs a) {
+    using R = typename SpinorIO<P>::R;
+    __shared__ double lds[kBlock / 64];
+    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+    double red = 0.0;
+    if (s < a.nsites) {
+        C<R> acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+        for (int j = 0; j < a.nv; ++j) {
+            C<R> x[12];
+            SpinorIO<P>::load(a.v[j], s, x);
+            const R c = (R)coefv(a.c[j]);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const R ck = (a.g5[j] && k >= 6) ? -c : c;
+                acc[k] = {acc[k].r + ck * x[k].r, acc[k].i + ck * x[k].i};
+            }
+        }
+        SpinorIO<P>::store(a.out, s, acc);
+        if (a.partials) {
+            if constexpr (P == P16) SpinorIO<P>::load(a.out, s, acc);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) red += (double)acc[k].r * acc[k].r + (double)acc[k].i * acc[k].i;
+        }
+    }
+    if (a.partials) {
+        const double t = block_sum(red, lds);
+        if (threadIdx.x == 0) a.partials[blockIdx.x] = t;
+    }
+}
+
+// dst[j] = sum_b partials[b * nvals + j], blocks added in index order.
+__global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partials, int nblocks, int nvals,
+                                                   double* __restrict__ dst) {
+    __shared__ double lds[kBlock / 64];
+    for (int j = 0; j < nvals; ++j) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partials[(int64_t)b * nvals + j];
+        s = block_sum(s, lds);
+        if (threadIdx.x == 0) dst[j] = s;
+        __syncthreads();
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_dot(SpinorView x, SpinorView y, int has_y, int32_t n,
+                                                double* __restrict__ partials) {
+    using R = typename SpinorIO<P>::R;
+    __shared__ double lds[kBlock / 64];
+    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+    double re = 0.0, im = 0.0;
+    if (s < n) {
+        C<R> a[12];
+        SpinorIO<P>::load(x, s, a);
+        if (has_y) {
+            C<R> b[12];
+            SpinorIO<P>::load(y, s, b);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                re += (double)a[k].r * b[k].r + (double)a[k].i * b[k].i;
+                im += (double)a[k].r * b[k].i - (double)a[k].i * b[k].r;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) re += (double)a[k].r * a[k].r + (double)a[k].i * a[k].i;
+        }
+    }
+    const double sr = block_sum(re, lds);
+    __syncthreads();
+    if (has_y) {
+        const double si = block_sum(im, lds);
+        if (threadIdx.x == 0) {
+            partials[2 * blockIdx.x] = sr;
+            partials[2 * blockIdx.x + 1] = si;
+        }
+    } else if (threadIdx.x == 0) {
+        partials[blockIdx.x] = sr;
+    }
+}
+
+template <int PD, int PS>
+__global__ void __launch_bounds__(kBlock) k_convert(SpinorView dst, SpinorView src, int32_t n) {
+    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    using RS = typename SpinorIO<PS>::R;
+    using RD = typename SpinorIO<PD>::R;
+    C<RS> a[12];
+    SpinorIO<PS>::load(src, s, a);
+    C<RD> b[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) b[k] = {(RD)a[k].r, (RD)a[k].i};
+    SpinorIO<PD>::store(dst, s, b);
+}
+
+// ---- low-mode projection ----------------------------------------------------
+
+// partials[block][2k + {0,1}] = sum over the block's sites of <u_k, v>.
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_mode_dots(const char* __restrict__ modes, int64_t mode_bytes, int nev,
+                                                      SpinorView v, SpinorView um, int32_t n,
+                                                      double* __restrict__ partials) {
+    using R = typename SpinorIO<P>::R;
+    __shared__ double lds[kBlock / 64][2 * NDQ_MAX_MODES];
+    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    C<double> x[12];
+    if (s < n) {
+        C<R> t[12];
+        SpinorIO<P>::load(v, s, t);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) x[k] = {(double)t[k].r, (double)t[k].i};
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) x[k] = {0.0, 0.0};
+    }
+    for (int m = 0; m < nev; ++m) {
+        double re = 0.0, im = 0.0;
+        if (s < n) {
+            SpinorView u = um;
+            u.base = const_cast<char*>(modes) + (int64_t)m * mode_bytes;
+            C<double> w[12];
+            SpinorIO<P64>::load(u, s, w);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                re += w[k].r * x[k].r + w[k].i * x[k].i;
+                im += w[k].r * x[k].i - w[k].i * x[k].r;
+            }
+        }
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) {
+            lds[wave][2 * m] = re;
+            lds[wave][2 * m + 1] = im;
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < 2 * nev; j += kBlock) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += lds[w][j];
+        partials[(int64_t)blockIdx.x * 2 * nev + j] = t;
+    }
+}
+
+// out = in + sum_k coef_k u_k
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_mode_update(const char* __restrict__ modes, int64_t mode_bytes, int nev,
+                                                        const double* __restrict__ coef, SpinorView in,
+                                                        SpinorView out, SpinorView um, int32_t n) {
+    using R = typename SpinorIO<P>::R;
+    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    C<R> t[12];
+    SpinorIO<P>::load(in, s, t);
+    C<double> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {(double)t[k].r, (double)t[k].i};
+    for (int m = 0; m < nev; ++m) {
+        const C<double> c = {coef[2 * m], coef[2 * m + 1]};
+        SpinorView u = um;
+        u.base = const_cast<char*>(modes) + (int64_t)m * mode_bytes;
+        C<double> w[12];
+        SpinorIO<P64>::load(u, s, w);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = cfma(acc[k], c, w[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) t[k] = {(R)acc[k].r, (R)acc[k].i};
+    SpinorIO<P>::store(out, s, t);
+}
+
+// ---- multi-shift CG ------------------------------------------------------------
+// Shifted systems (A + sigma_l) x_l = b, A = X^2, solved on the Krylov space of
+// the smallest shift sigma_0: the shifted residuals stay collinear,
+// r_l = zeta_l r, with
+//   zeta_l' = zeta_l zeta_l^- a^- / (a b^- (zeta_l^- - zeta_l) + zeta_l^- a^- (1 + (sigma_l - sigma_0) a)),
+//   a_l = a zeta_l'/zeta_l,  b_l = b (zeta_l'/zeta_l)^2,
+//   x_l += a_l p_l,  p_l = zeta_l' r + b_l p_l
+// (Jegerlehner, hep-lat/9612014).  Only y = sum_l w_l x_l is accumulated.  A
+// shift is frozen once |zeta_l| |r| <= tol |b|.
+
+__device__ double block_reduce_partials(const double* partials, int nblocks, double* lds) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partials[b];
+    return block_sum(s, lds);
+}
+
+__global__ void __launch_bounds__(kBlock) k_ms_init(MsState* st, MsConst k, const double* b2p, int nblk) {
+    __shared__ double lds[kBlock / 64];
+    const double b2 = block_reduce_partials(b2p, nblk, lds);
+    if (threadIdx.x == 0) {
+        st->b2 = b2;
+        st->rr = b2;
+        st->pp = b2;
+        st->alpha_prev = 1.0;
+        st->beta_prev = 0.0;
+        st->iter = 0;
+        st->done = (b2 == 0.0);
+        st->bad = !isfinite(b2);
+        for (int l = 0; l < NDQ_MAX_SHIFTS; ++l) {
+            st->zeta[l] = st->zeta_prev[l] = 1.0;
+            st->upd_p[l] = l < k.n;
+            st->upd_y[l] = 0;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_ms_alpha(MsState* st, MsConst k, const double* ttp, int nblk_tt,
+                                                     const double* ppp, int nblk_pp) {
+    __shared__ double lds[kBlock / 64];
+    const double tt = block_reduce_partials(ttp, nblk_tt, lds);
+    __syncthreads();
+    double pp = 0.0;
+    if (ppp) pp = block_reduce_partials(ppp, nblk_pp, lds);
+    if (threadIdx.x != 0) return;
+    if (st->done) {
+        // converged: leave every vector unchanged until the host notices
+        st->c0 = 0.0;
+        st->cp = 0.0;
+        for (int l = 0; l < k.n; ++l) {
+            st->upd_y[l] = 0;
+            st->upd_p[l] = 0;
+        }
+        return;
+    }
+    if (ppp) st->pp = pp;
+    st->tt = tt;
+    const double denom = tt * k.inv_lam2 + k.sigma[0] * st->pp;
+    const double a = st->rr / denom;
+    if (!isfinite(a)) st->bad = 1;
+    st->alpha = a;
+    for (int l = 0; l < k.n; ++l) {
+        if (!st->upd_p[l]) {
+            st->upd_y[l] = 0;
+            st->ycoef[l] = 0.0;
+            continue;
+        }
+        double zn = 1.0;
+        if (l > 0) {
+            const double d = k.sigma[l] - k.sigma[0];
+            const double den = a * st->beta_prev * (st->zeta_prev[l] - st->zeta[l]) +
+                               st->zeta_prev[l] * st->alpha_prev * (1.0 + d * a);
+            zn = st->zeta[l] * st->zeta_prev[l] * st->alpha_prev / den;
+        }
+        st->zeta_new[l] = zn;
+        st->ycoef[l] = k.w[l] * a * zn / st->zeta[l];
+        st->upd_y[l] = 1;
+    }
+    st->c0 = -a * k.inv_lam2;
+    st->cp = -a * k.sigma[0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_ms_beta(MsState* st, MsConst k, const double* rrp, int nblk) {
+    __shared__ double lds[kBlock / 64];
+    const double rr = block_reduce_partials(rrp, nblk, lds);
+    if (threadIdx.x != 0 || st->done) return;
+    const double b = rr / st->rr;
+    if (!isfinite(b)) st->bad = 1;
+    for (int l = 0; l < k.n; ++l) {
+        if (!st->upd_y[l]) {
+            st->upd_p[l] = 0;
+            continue;
+        }
+        const double q = st->zeta_new[l] / st->zeta[l];
+        st->bl[l] = b * q * q;
+        st->pcoef[l] = st->zeta_new[l];
+        st->zeta_prev[l] = st->zeta[l];
+        st->zeta[l] = st->zeta_new[l];
+        st->upd_p[l] = st->zeta[l] * st->zeta[l] * rr > k.tol2 * st->b2;
+    }
+    st->alpha_prev = st->alpha;
+    st->beta_prev = b;
+    st->rr = rr;
+    st->iter += 1;
+    st->done = rr <= k.tol2 * st->b2;
+}
+
+struct MsUpdArgs {
+    SpinorView r, y;
+    SpinorView p0;
+    int64_t p_bytes;
+    int n;
+    int32_t nsites;
+    const MsState* st;
+    double* partials;
+};
+
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_ms_update(MsUpdArgs a) {
+    using R = typename SpinorIO<P>::R;
+    __shared__ double lds[kBlock / 64];
+    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+    double red = 0.0;
+    if (s < a.nsites) {
+        C<R> r[12], y[12];
+        SpinorIO<P>::load(a.r, s, r);
+        SpinorIO<P>::load(a.y, s, y);
+        for (int l = 0; l < a.n; ++l) {
+            const int uy = a.st->upd_y[l], up = a.st->upd_p[l];
+            if (!uy && !up) continue;
+            SpinorView pv = a.p0;
+            pv.base += (int64_t)l * a.p_bytes;
+            C<R> p[12];
+            SpinorIO<P>::load(pv, s, p);
+            if (uy) {
+                const R c = (R)a.st->ycoef[l];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) y[k] = {y[k].r + c * p[k].r, y[k].i + c * p[k].i};
+            }
+            if (up) {
+                const R zc = (R)a.st->pcoef[l], bc = (R)a.st->bl[l];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) p[k] = {zc * r[k].r + bc * p[k].r, zc * r[k].i + bc * p[k].i};
+                SpinorIO<P>::store(pv, s, p);
+                if (l == 0) {
+                    if constexpr (P == P16) SpinorIO<P>::load(pv, s, p);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) red += (double)p[k].r * p[k].r + (double)p[k].i * p[k].i;
+                }
+            }
+        }
+        SpinorIO<P>::store(a.y, s, y);
+    }
+    if (a.partials) {
+        const double t = block_sum(red, lds);
+        if (threadIdx.x == 0) a.partials[blockIdx.x] = t;
+    }
+}
+
+__global__ void k_mode_coef(const double* c, const double* d, ModeSigns sg, int use_sign, int nev, double sc,
+                            double sd, double* coef) {
+    const int k = threadIdx.x;
+    if (k >= nev) return;
+    const double f = sc * (use_sign ? (double)sg.s[k] : 1.0);
+    coef[2 * k] = f * c[2 * k] + (d ? sd * d[2 * k] : 0.0);
+    coef[2 * k + 1] = f * c[2 * k + 1] + (d ? sd * d[2 * k + 1] : 0.0);
+}
+
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+namespace ndq {
+
+int lincomb_blocks(const ndq_geom* g) { return (int)nblocks(g->volume); }
+
+size_t partials_capacity(const ndq_geom* g, int nvals) {
+    const int64_t blocks = std::max<int64_t>(nblocks(g->volume), 2 * ((g->vh + 63) / 64));
+    return (size_t)blocks * (size_t)std::max(nvals, 1) * sizeof(double);
+}
+
+int lincomb(const ndq_geom* g, int prec, const ndq_spinor* out, int nv, const ndq_spinor* const* v, const Coef* c,
+            const int* g5, double* partials, hipStream_t st) {
+    LinArgs a;
+    memset(&a, 0, sizeof(a));
+    a.out = flat_view(g, out);
+    a.nv = nv;
+    for (int j = 0; j < nv; ++j) {
+        a.v[j] = flat_view(g, v[j]);
+        a.c[j] = c[j];
+        a.g5[j] = g5 ? g5[j] : 0;
+    }
+    a.nsites = (int32_t)g->volume;
+    a.partials = partials;
+    const dim3 grid(nblocks(g->volume));
+    switch (prec) {
+        case NDQ_F64: hipLaunchKernelGGL(k_lincomb<P64>, grid, dim3(kBlock), 0, st, a); break;
+        case NDQ_F32: hipLaunchKernelGGL(k_lincomb<P32>, grid, dim3(kBlock), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_lincomb<P16>, grid, dim3(kBlock), 0, st, a); break;
+    }
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int reduce_partials(const double* partials, int nb, int nvals, double* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, partials, nb, nvals, dst);
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int dot(const ndq_geom* g, const ndq_spinor* x, const ndq_spinor* y, double* partials, double* dst, hipStream_t st) {
+    const SpinorView xv = flat_view(g, x);
+    const SpinorView yv = y ? flat_view(g, y) : xv;
+    const int32_t n = (int32_t)g->volume;
+    const dim3 grid(nblocks(n));
+    const int hy = y != nullptr;
+    switch (x->prec) {
+        case NDQ_F64: hipLaunchKernelGGL(k_dot<P64>, grid, dim3(kBlock), 0, st, xv, yv, hy, n, partials); break;
+        case NDQ_F32: hipLaunchKernelGGL(k_dot<P32>, grid, dim3(kBlock), 0, st, xv, yv, hy, n, partials); break;
+        default: hipLaunchKernelGGL(k_dot<P16>, grid, dim3(kBlock), 0, st, xv, yv, hy, n, partials); break;
+    }
+    NDQ_HIP(hipGetLastError());
+    return reduce_partials(partials, (int)grid.x, hy ? 2 : 1, dst, st);
+}
+
+int convert(const ndq_geom* g, const ndq_spinor* dst, const ndq_spinor* src, hipStream_t st) {
+    const SpinorView d = flat_view(g, dst), s = flat_view(g, src);
+    const int32_t n = (int32_t)g->volume;
+    const dim3 grid(nblocks(n));
+    const int key = dst->prec * 3 + src->prec;
+    switch (key) {
+        case NDQ_F64 * 3 + NDQ_F64: hipLaunchKernelGGL((k_convert<P64, P64>), grid, dim3(kBlock), 0, st, d, s, n); break;
+        case NDQ_F64 * 3 + NDQ_F32: hipLaunchKernelGGL((k_convert<P64, P32>), grid, dim3(kBlock), 0, st, d, s, n); break;
+        case NDQ_F64 * 3 + NDQ_F16: hipLaunchKernelGGL((k_convert<P64, P16>), grid, dim3(kBlock), 0, st, d, s, n); break;
+        case NDQ_F32 * 3 + NDQ_F64: hipLaunchKernelGGL((k_convert<P32, P64>), grid, dim3(kBlock), 0, st, d, s, n); break;
+        case NDQ_F32 * 3 + NDQ_F32: hipLaunchKernelGGL((k_convert<P32, P32>), grid, dim3(kBlock), 0, st, d, s, n); break;
+        case NDQ_F32 * 3 + NDQ_F16: hipLaunchKernelGGL((k_convert<P32, P16>), grid, dim3(kBlock), 0, st, d, s, n); break;
+        case NDQ_F16 * 3 + NDQ_F64: hipLaunchKernelGGL((k_convert<P16, P64>), grid, dim3(kBlock), 0, st, d, s, n); break;
+        case NDQ_F16 * 3 + NDQ_F32: hipLaunchKernelGGL((k_convert<P16, P32>), grid, dim3(kBlock), 0, st, d, s, n); break;
+        default: hipLaunchKernelGGL((k_convert<P16, P16>), grid, dim3(kBlock), 0, st, d, s, n); break;
+    }
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int mode_dots(const ndq_geom* g, const void* modes, int nev, const ndq_spinor* v, double* partials, double* dots,
+              hipStream_t st) {
+    if (nev <= 0) return NDQ_OK;
+    const int32_t n = (int32_t)g->volume;
+    const dim3 grid(nblocks(n));
+    const SpinorView vv = flat_view(g, v);
+    ndq_spinor um_desc = {const_cast<void*>(modes), NDQ_F64, NDQ_FULL, 1};
+    const SpinorView um = flat_view(g, &um_desc);
+    const int64_t mb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
+    const char* mp = static_cast<const char*>(modes);
+    switch (v->prec) {
+        case NDQ_F64: hipLaunchKernelGGL(k_mode_dots<P64>, grid, dim3(kBlock), 0, st, mp, mb, nev, vv, um, n, partials); break;
+        case NDQ_F32: hipLaunchKernelGGL(k_mode_dots<P32>, grid, dim3(kBlock), 0, st, mp, mb, nev, vv, um, n, partials); break;
+        default: hipLaunchKernelGGL(k_mode_dots<P16>, grid, dim3(kBlock), 0, st, mp, mb, nev, vv, um, n, partials); break;
+    }
+    NDQ_HIP(hipGetLastError());
+    return reduce_partials(partials, (int)grid.x, 2 * nev, dots, st);
+}
+
+int mode_update(const ndq_geom* g, const void* modes, int nev, const double* coef, const ndq_spinor* in,
+                const ndq_spinor* out, hipStream_t st) {
+    const int32_t n = (int32_t)g->volume;
+    const dim3 grid(nblocks(n));
+    const SpinorView iv = flat_view(g, in), ov = flat_view(g, out);
+    ndq_spinor um_desc = {const_cast<void*>(modes), NDQ_F64, NDQ_FULL, 1};
+    const SpinorView um = flat_view(g, &um_desc);
+    const int64_t mb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
+    const char* mp = static_cast<const char*>(modes);
+    switch (in->prec) {
+        case NDQ_F64: hipLaunchKernelGGL(k_mode_update<P64>, grid, dim3(kBlock), 0, st, mp, mb, nev, coef, iv, ov, um, n); break;
+        case NDQ_F32: hipLaunchKernelGGL(k_mode_update<P32>, grid, dim3(kBlock), 0, st, mp, mb, nev, coef, iv, ov, um, n); break;
+        default: hipLaunchKernelGGL(k_mode_update<P16>, grid, dim3(kBlock), 0, st, mp, mb, nev, coef, iv, ov, um, n); break;
+    }
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int mode_coef(const double* c, const double* d, const ModeSigns& sg, int use_sign, int nev, double sc, double sd,
+              double* coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_mode_coef, dim3(1), dim3(NDQ_MAX_MODES), 0, st, c, d, sg, use_sign, nev, sc, sd, coef);
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int ms_init(MsState* s, const MsConst& k, const double* b2p, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(kBlock), 0, st, s, k, b2p, nblk);
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int ms_alpha(MsState* s, const MsConst& k, const double* ttp, int nblk_tt, const double* ppp, int nblk_pp,
+             hipStream_t st) {
+    hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(kBlock), 0, st, s, k, ttp, nblk_tt, ppp, nblk_pp);
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int ms_beta(MsState* s, const MsConst& k, const double* rrp, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(kBlock), 0, st, s, k, rrp, nblk);
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int ms_update(const ndq_geom* g, int prec, MsState* s, const MsConst& k, const ndq_spinor* r, const ndq_spinor* y,
+              const ndq_spinor* p, double* partials, hipStream_t st) {
+    MsUpdArgs a;
+    a.r = flat_view(g, r);
+    a.y = flat_view(g, y);
+    a.p0 = flat_view(g, p);
+    a.p_bytes = spinor_rhs_bytes(g, prec, NDQ_FULL);
+    a.n = k.n;
+    a.nsites = (int32_t)g->volume;
+    a.st = s;
+    a.partials = partials;
+    const dim3 grid(nblocks(g->volume));
+    switch (prec) {
+        case NDQ_F64: hipLaunchKernelGGL(k_ms_update<P64>, grid, dim3(kBlock), 0, st, a); break;
+        case NDQ_F32: hipLaunchKernelGGL(k_ms_update<P32>, grid, dim3(kBlock), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_ms_update<P16>, grid, dim3(kBlock), 0, st, a); break;
+    }
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+}  // namespace ndq

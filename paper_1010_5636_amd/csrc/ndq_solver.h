@@ -1,0 +1,127 @@
+// Internal interfaces of the sign-function, D_N and solver layers.
+#pragma once
+
+#include <vector>
+
+#include "ndq_internal.h"
+#include "wilson.h"
+
+#define NDQ_MAX_SHIFTS 32
+#define NDQ_MAX_MODES 64
+
+namespace ndq {
+
+struct Approx {
+    int kind;                 // NDQ_ZOLOTAREV or NDQ_MINMAX_POLY
+    int n;                    // poles, or polynomial degree
+    double lo;                // k (Zolotarev, on |x|) or eps (polynomial, on y = x^2)
+    double delta;             // max approximation error on the interval
+    std::vector<double> a;    // sigma_l (ascending) or c_0..c_n
+    std::vector<double> b;    // beta_l (Zolotarev only)
+};
+
+// Bump allocator over the caller's workspace (256-byte aligned pieces).
+struct Arena {
+    char* base;
+    size_t size;
+    size_t used = 0;
+    bool overflow = false;
+    void* take(size_t bytes) {
+        const size_t off = (used + 255) & ~size_t(255);
+        if (off + bytes > size || base == nullptr) {
+            overflow = true;
+            used = off + bytes;
+            return nullptr;
+        }
+        used = off + bytes;
+        return base + off;
+    }
+};
+
+// A full (both parities), single right-hand-side spinor in workspace memory.
+inline ndq_spinor ws_spinor(Arena& ar, const ndq_geom* g, int prec) {
+    ndq_spinor s;
+    s.data = ar.take((size_t)spinor_rhs_bytes(g, prec, NDQ_FULL));
+    s.prec = prec;
+    s.parity = NDQ_FULL;
+    s.nrhs = 1;
+    return s;
+}
+
+// View of a whole full spinor as V consecutive sites (for site-local kernels).
+inline SpinorView flat_view(const ndq_geom* g, const ndq_spinor* s, int rhs = 0) {
+    SpinorView v = view_of(g, s, 0, rhs);
+    v.stride = (int32_t)g->volume;
+    v.site0 = 0;
+    return v;
+}
+
+// ---- BLAS-1 and reductions (blas.hip) --------------------------------------
+// Upper bound on the per-block partial sums any kernel below writes.
+size_t partials_capacity(const ndq_geom* g, int nvals);
+
+// out = sum_k c_k G5^{g5_k} v_k (k < nv <= 4), optional |out|^2 partials.
+// All vectors full fields of precision `prec`; out may alias a v_k.
+int lincomb(const ndq_geom* g, int prec, const ndq_spinor* out, int nv, const ndq_spinor* const* v,
+            const Coef* c, const int* g5, double* partials, hipStream_t st);
+// Sum per-block partials into dst (nvals interleaved values per block).
+int reduce_partials(const double* partials, int nblocks, int nvals, double* dst, hipStream_t st);
+int lincomb_blocks(const ndq_geom* g);
+// <x, y> (complex, FP64 accumulation) into dst[0..1]; |x|^2 into dst if y == nullptr.
+int dot(const ndq_geom* g, const ndq_spinor* x, const ndq_spinor* y, double* partials, double* dst, hipStream_t st);
+// Precision conversion between full fields (same site layout).
+int convert(const ndq_geom* g, const ndq_spinor* dst, const ndq_spinor* src, hipStream_t st);
+
+// Low modes: dots[k] = <u_k, v> for the nev packed F64 full spinors at `modes`.
+int mode_dots(const ndq_geom* g, const void* modes, int nev, const ndq_spinor* v, double* partials,
+              double* dots, hipStream_t st);
+// coef_k = sc * (use_sign ? sign_k : 1) * c_k + sd * d_k (complex, device arrays of 2*nev doubles).
+struct ModeSigns {
+    float s[NDQ_MAX_MODES];
+};
+int mode_coef(const double* c, const double* d, const ModeSigns& sg, int use_sign, int nev, double sc, double sd,
+              double* coef, hipStream_t st);
+// out = in + sum_k coef_k u_k (coef complex, device array of 2*nev doubles).
+int mode_update(const ndq_geom* g, const void* modes, int nev, const double* coef, const ndq_spinor* in,
+                const ndq_spinor* out, hipStream_t st);
+
+// ---- multi-shift CG device state (blas.hip) ---------------------------------
+struct MsState {
+    double b2;                        // |b|^2
+    double rr;                        // |r|^2
+    double tt;                        // |Q p_s|^2
+    double pp;                        // |p_s|^2
+    double alpha, alpha_prev, beta_prev;
+    double c0, cp;                    // epilogue coefficients of the residual update
+    double zeta[NDQ_MAX_SHIFTS], zeta_prev[NDQ_MAX_SHIFTS], zeta_new[NDQ_MAX_SHIFTS];
+    double ycoef[NDQ_MAX_SHIFTS], pcoef[NDQ_MAX_SHIFTS], bl[NDQ_MAX_SHIFTS];
+    int upd_y[NDQ_MAX_SHIFTS], upd_p[NDQ_MAX_SHIFTS];
+    int iter, done, bad;
+};
+
+struct MsConst {
+    int n;
+    double inv_lam2;                  // 1 / lam_max^2
+    double tol2;                      // tol^2
+    double sigma[NDQ_MAX_SHIFTS];
+    double w[NDQ_MAX_SHIFTS];         // residues
+};
+
+int ms_init(MsState* st_dev, const MsConst& k, const double* b2_partials, int nblk, hipStream_t st);
+int ms_alpha(MsState* st_dev, const MsConst& k, const double* tt_partials, int nblk_tt, const double* pp_partials,
+             int nblk_pp, hipStream_t st);
+int ms_beta(MsState* st_dev, const MsConst& k, const double* rr_partials, int nblk, hipStream_t st);
+int ms_update(const ndq_geom* g, int prec, MsState* st_dev, const MsConst& k, const ndq_spinor* r,
+              const ndq_spinor* y, const ndq_spinor* p, double* partials, hipStream_t st);
+
+// ---- sign and D_N (sign.cpp) --------------------------------------------------
+size_t sign_workspace(const ndq_geom* g, const ndq_overlap_params* p, int prec);
+int apply_sign(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p, const ndq_spinor* in,
+               const ndq_spinor* out, Arena& ar, ndq_stats* stats, hipStream_t st);
+
+// Stencil helper: out = c0 * Q in + sum_k cv_k v_k (full fields), optional partials.
+int q_combo(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in, const ndq_spinor* out,
+            Coef c0, int nv, const ndq_spinor* const* v, const Coef* cv, double* partials, hipStream_t st);
+int q_blocks(const ndq_geom* g, const ndq_gauge* U, int sprec);
+
+}  // namespace ndq

@@ -22,6 +22,7 @@ F64, F32, F16 = 0, 1, 2
 EVEN, ODD, FULL = 0, 1, 2
 ZOLOTAREV, MINMAX_POLY = 0, 1
 LITERAL, SANDWICH = 0, 1
+OP_SIGN, OP_DN, OP_SOLVE = 0, 1, 2
 
 STATUS = {0: "NDQ_OK", -1: "NDQ_EINVAL", -2: "NDQ_EDIMS", -3: "NDQ_EPREC", -4: "NDQ_ENOMEM",
           -5: "NDQ_ESINGULAR", -6: "NDQ_ENOCONV", -7: "NDQ_ENAN", -8: "NDQ_EHIP"}
@@ -40,6 +41,21 @@ class _Gauge(ctypes.Structure):
 class _Spinor(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("prec", ctypes.c_int32), ("parity", ctypes.c_int32),
                 ("nrhs", ctypes.c_int32)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_double), ("mq", ctypes.c_double), ("lam_max", ctypes.c_double),
+                ("approx", ctypes.c_void_p), ("modes", ctypes.c_void_p), ("nu", ctypes.POINTER(ctypes.c_double)),
+                ("nev", ctypes.c_int32), ("form", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("q_applies", ctypes.c_int64), ("iterations", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("inner", ctypes.c_int64), ("residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _P = ctypes.c_void_p
@@ -63,6 +79,16 @@ _SIG = {
     "ndq_apply_dslash": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P]),
     "ndq_apply_Qhat_ee": (_I, [_P, ctypes.POINTER(_Gauge), _D, ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor),
                                ctypes.POINTER(_Spinor), _P]),
+    "ndq_approx_create": (_I, [_I, _D, _I, ctypes.POINTER(_P)]),
+    "ndq_approx_from_coeffs": (_I, [_I, _I, ctypes.POINTER(_D), ctypes.POINTER(_D), _D, _D, ctypes.POINTER(_P)]),
+    "ndq_approx_info": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "ndq_approx_coeffs": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "ndq_approx_destroy": (None, [_P]),
+    "ndq_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(_Params), _I, _I]),
+    "ndq_apply_sign": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Params), ctypes.POINTER(_Spinor),
+                            ctypes.POINTER(_Spinor), _P, ctypes.c_size_t, ctypes.POINTER(_Stats), _P]),
+    "ndq_apply_DN": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Params), ctypes.POINTER(_Spinor),
+                          ctypes.POINTER(_Spinor), _P, ctypes.c_size_t, ctypes.POINTER(_Stats), _P]),
     "ndq_set_launch": (_I, [_I, _I]),
     "ndq_set_launch_for": (_I, [_I, _I, _I, _I, _I]),
 }
@@ -228,3 +254,92 @@ def apply_Qhat_ee(geom: Geometry, U: GaugeField, m: float, inp: SpinorField, out
                   tmp: SpinorField, stream=None):
     _check(lib().ndq_apply_Qhat_ee(geom.handle, ctypes.byref(U.desc), float(m), ctypes.byref(inp.desc),
                                    ctypes.byref(out.desc), ctypes.byref(tmp.desc), _stream(stream)))
+
+
+class Approx:
+    """Host handle of a sign approximant (ndq_approx)."""
+
+    def __init__(self, kind: int, lo: float, degree: int, _handle=None):
+        if _handle is None:
+            h = ctypes.c_void_p()
+            _check(lib().ndq_approx_create(kind, float(lo), int(degree), ctypes.byref(h)))
+            _handle = h
+        self.handle = _handle
+        k, n, lo_, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().ndq_approx_info(self.handle, ctypes.byref(k), ctypes.byref(n), ctypes.byref(lo_), ctypes.byref(d)))
+        self.kind, self.n, self.lo, self.delta = k.value, n.value, lo_.value, d.value
+
+    @classmethod
+    def from_coeffs(cls, kind: int, a, b=None, lo: float = 0.0, delta: float = 0.0):
+        import numpy as np
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        n = len(a) if kind == ZOLOTAREV else len(a) - 1
+        bp = None
+        if b is not None:
+            b = np.ascontiguousarray(b, dtype=np.float64)
+            bp = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h = ctypes.c_void_p()
+        _check(lib().ndq_approx_from_coeffs(kind, n, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), bp,
+                                            float(lo), float(delta), ctypes.byref(h)))
+        return cls(kind, lo, n, _handle=h)
+
+    def coeffs(self):
+        import numpy as np
+        na = self.n if self.kind == ZOLOTAREV else self.n + 1
+        a = np.zeros(na)
+        b = np.zeros(self.n) if self.kind == ZOLOTAREV else None
+        _check(lib().ndq_approx_coeffs(self.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       None if b is None else b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return a, b
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.ndq_approx_destroy(self.handle)
+            self.handle = None
+
+
+class Overlap:
+    """Parameters of sign(Q) / D_N (ndq_overlap_params) plus the device workspace.
+
+    ``modes``: a SpinorField (F64, FULL, nrhs = nev) of orthonormal Rayleigh-Ritz
+    vectors; ``nu``: their eigenvalues."""
+
+    def __init__(self, geom: Geometry, m: float, approx: Approx, lam_max: float, modes: "SpinorField | None" = None,
+                 nu=None, mq: float = 0.0, form: int = LITERAL, tol: float = 1e-12, max_iter: int = 100000,
+                 check_every: int = 8):
+        import numpy as np
+        self.geom, self.approx, self.modes = geom, approx, modes
+        nev = 0 if modes is None else modes.nrhs
+        if modes is not None and (modes.prec != F64 or modes.parity != FULL):
+            raise NdqError(-1, "low modes must be F64 FULL spinor fields")
+        self.nu = np.ascontiguousarray(np.zeros(1) if nu is None else nu, dtype=np.float64)
+        self.p = _Params(float(m), float(mq), float(lam_max), approx.handle.value,
+                         None if modes is None else modes.buf.data_ptr(),
+                         self.nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nev, form, float(tol),
+                         int(max_iter), int(check_every))
+        self._ws = {}
+
+    def workspace(self, prec: int, op: int):
+        key = (prec, op)
+        if key not in self._ws:
+            n = int(lib().ndq_workspace_bytes(self.geom.handle, ctypes.byref(self.p), prec, op))
+            if n == 0:
+                raise NdqError(-1, "invalid parameters for ndq_workspace_bytes")
+            self._ws[key] = torch.empty(n, dtype=torch.uint8, device="cuda")
+        return self._ws[key]
+
+
+def apply_sign(geom: Geometry, U: GaugeField, ov: Overlap, inp: SpinorField, out: SpinorField, stream=None) -> dict:
+    ws = ov.workspace(inp.prec, OP_SIGN)
+    st = _Stats()
+    _check(lib().ndq_apply_sign(geom.handle, ctypes.byref(U.desc), ctypes.byref(ov.p), ctypes.byref(inp.desc),
+                                ctypes.byref(out.desc), _ptr(ws), ws.numel(), ctypes.byref(st), _stream(stream)))
+    return st.as_dict()
+
+
+def apply_DN(geom: Geometry, U: GaugeField, ov: Overlap, inp: SpinorField, out: SpinorField, stream=None) -> dict:
+    ws = ov.workspace(inp.prec, OP_DN)
+    st = _Stats()
+    _check(lib().ndq_apply_DN(geom.handle, ctypes.byref(U.desc), ctypes.byref(ov.p), ctypes.byref(inp.desc),
+                              ctypes.byref(out.desc), _ptr(ws), ws.numel(), ctypes.byref(st), _stream(stream)))
+    return st.as_dict()

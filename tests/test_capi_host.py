@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -94,3 +95,37 @@ def test_descriptor_validation_before_launch(ndq):
     rc = lib.ndq_gauge_pack(g.handle, ctypes.c_void_p(fake), ctypes.byref(f16_8), None)
     assert rc == -3
     assert "F16" in lib.ndq_last_error().decode()
+
+
+@pytest.mark.parametrize("k,n", [(0.0909, 10), (0.05, 6), (0.3, 1), (0.2, 16)])
+def test_zolotarev_library_vs_oracle(ndq, k, n):
+    """Host-side approximant of the library against the oracle's independent one."""
+    from oracle import approx
+    a = ndq.Approx(ndq.ZOLOTAREV, k, n)
+    sig, beta = a.coeffs()
+    ref = approx.zolotarev(k, n)
+    assert np.allclose(sig, ref.sigma, rtol=1e-12, atol=0)
+    assert np.allclose(beta, ref.beta, rtol=1e-12, atol=0)
+    assert abs(a.delta - ref.delta) <= 1e-6 * ref.delta + 1e-14
+
+
+@pytest.mark.parametrize("eps,n", [(0.0909 ** 2, 40), (0.05 ** 2, 100), (0.01, 0), (0.2 ** 2, 7)])
+def test_minmax_library_vs_oracle(ndq, eps, n):
+    from oracle import approx
+    a = ndq.Approx(ndq.MINMAX_POLY, eps, n)
+    c, _ = a.coeffs()
+    ref = approx.minimax_polynomial(eps, n)
+    assert np.abs(c - ref.c).max() <= 1e-10 * np.abs(ref.c).max()
+    assert abs(a.delta - ref.delta) <= 1e-6 * ref.delta + 1e-14
+
+
+def test_approx_validation(ndq):
+    with pytest.raises(ndq.NdqError):
+        ndq.Approx(ndq.ZOLOTAREV, 1.5, 4)
+    with pytest.raises(ndq.NdqError):
+        ndq.Approx(ndq.ZOLOTAREV, 0.1, 0)
+    with pytest.raises(ndq.NdqError):
+        ndq.Approx(7, 0.1, 3)
+    a = ndq.Approx.from_coeffs(ndq.MINMAX_POLY, [1.0, 0.5, 0.25], lo=0.01, delta=0.1)
+    assert a.n == 2 and abs(a.delta - 0.1) < 1e-15
+    assert np.allclose(a.coeffs()[0], [1.0, 0.5, 0.25])
