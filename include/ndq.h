@@ -215,6 +215,50 @@ int ndq_apply_DN(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params
                  const ndq_spinor* in, const ndq_spinor* out, void* ws, size_t ws_bytes,
                  ndq_stats* stats, void* stream);
 
+/* ---- low modes of Q (FP64) ----------------------------------------------- */
+typedef struct {
+    int32_t nev;          /* number l of low modes of Q to return (>= 1)                      */
+    int32_t nextra;       /* extra Ritz vectors carried as a guard band (>= 1)                */
+    int32_t basis;        /* Lanczos basis size m, nev + nextra + 2 <= m <= 63                */
+    int32_t cheb_degree;  /* degree d of the Chebyshev filter (even); <= 0: automatic        */
+    double cheb_lo;       /* filter cutoff a on Q^2; <= 0: from a plain Lanczos run           */
+    double tol;           /* stop when every rho_k <= tol * lam_max                          */
+    int32_t max_restarts; /* restart cycles (<= 0: 50)                                        */
+} ndq_lowmode_params;
+
+typedef struct {
+    double lam_next;      /* smallest |nu| of the Rayleigh-Ritz values not returned          */
+    double kappa_plus;    /* Eq. 9, with d_k = min(lam_next - |nu_k|, |nu_k| + min|nu_j| over */
+    double kappa_minus;   /*   the returned nu_j of opposite sign)                             */
+    double bound_plus;    /* Eq. 10: |P_+ - (P_+)_exact| <= kappa(1+2kappa)/(1-2kappa(1+2kappa)) */
+    double bound_minus;
+    double cheb_lo;       /* filter cutoff used                                               */
+    int32_t cheb_degree;  /* filter degree used                                               */
+    int32_t restarts;
+    int64_t q_applies;
+    double max_rho;
+    double seconds;
+} ndq_lowmode_info;
+
+size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params* p);
+
+/* The nev eigenmodes of Q closest to zero (Sec. 2.3): thick-restart Lanczos on a
+ * Chebyshev filter of Q^2 (FP64, full reorthogonalisation), then Rayleigh-Ritz of Q
+ * in the converged space (P Q u_k = nu_k u_k), residues rho_k = |(Q - nu_k) u_k|
+ * (Eq. 8) and kappa_+- (Eq. 9), bound (Eq. 10).
+ *   U: F64 links;  start: F64 NDQ_FULL spinor (nonzero);  d_modes: out, nev packed F64
+ *   NDQ_FULL spinors back to back (orthonormal);  nu, rho: host arrays of nev, sorted by
+ *   |nu| ascending.  Synchronises `stream`.  Errors: NDQ_ENOCONV (tol not reached; the
+ *   best modes found are still written), NDQ_ENOMEM, NDQ_EPREC, NDQ_ENAN. */
+int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double lam_max,
+                         const ndq_lowmode_params* p, const ndq_spinor* start, void* d_modes, double* nu,
+                         double* rho, ndq_lowmode_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Host utility: eigen-decomposition of a dense Hermitian n x n matrix (row-major,
+ * interleaved complex `a`, destroyed); w ascending, z columns = eigenvectors
+ * (row-major, interleaved complex).  The library's own small-matrix solver. */
+int ndq_host_eigh(int n, double* a, double* w, double* z);
+
 /* ---- launch tuning ------------------------------------------------------ */
 /* Launch shape of the stencil kernels: `block` = 64, 128 or 256 lanes with one
  * lane per output site, or 0 for the direction-split form (4 wavefronts per 64

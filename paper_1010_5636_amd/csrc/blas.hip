@@ -371,6 +371,42 @@ __global__ void k_mode_coef(const double* c, const double* d, ModeSigns sg, int 
     coef[2 * k + 1] = f * c[2 * k + 1] + (d ? sd * d[2 * k + 1] : 0.0);
 }
 
+// Basis rotation dst_j = sum_i src_i Y[i][j] for the FP64 full spinors of a
+// contiguous block (Y complex, row-major nsrc x k, on the device); each grid
+// row y computes the outputs j = 2y, 2y + 1.
+__global__ void __launch_bounds__(kBlock) k_rotate(const char* __restrict__ src, int nsrc, const double* __restrict__ Y,
+                                                   int k, char* __restrict__ dst, int64_t vbytes, SpinorView lay,
+                                                   int32_t n) {
+    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const int j0 = 2 * blockIdx.y;
+    const bool two = j0 + 1 < k;
+    C<double> a0[12], a1[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) a0[c] = a1[c] = {0.0, 0.0};
+    for (int i = 0; i < nsrc; ++i) {
+        SpinorView v = lay;
+        v.base = const_cast<char*>(src) + (int64_t)i * vbytes;
+        C<double> x[12];
+        SpinorIO<P64>::load(v, s, x);
+        const C<double> y0 = {Y[2 * ((int64_t)i * k + j0)], Y[2 * ((int64_t)i * k + j0) + 1]};
+#pragma unroll
+        for (int c = 0; c < 12; ++c) a0[c] = cfma(a0[c], y0, x[c]);
+        if (two) {
+            const C<double> y1 = {Y[2 * ((int64_t)i * k + j0 + 1)], Y[2 * ((int64_t)i * k + j0 + 1) + 1]};
+#pragma unroll
+            for (int c = 0; c < 12; ++c) a1[c] = cfma(a1[c], y1, x[c]);
+        }
+    }
+    SpinorView o = lay;
+    o.base = dst + (int64_t)j0 * vbytes;
+    SpinorIO<P64>::store(o, s, a0);
+    if (two) {
+        o.base += vbytes;
+        SpinorIO<P64>::store(o, s, a1);
+    }
+}
+
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -488,6 +524,17 @@ int mode_update(const ndq_geom* g, const void* modes, int nev, const double* coe
 int mode_coef(const double* c, const double* d, const ModeSigns& sg, int use_sign, int nev, double sc, double sd,
               double* coef, hipStream_t st) {
     hipLaunchKernelGGL(k_mode_coef, dim3(1), dim3(NDQ_MAX_MODES), 0, st, c, d, sg, use_sign, nev, sc, sd, coef);
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int rotate(const ndq_geom* g, const void* src, int nsrc, const double* Y, int k, void* dst, hipStream_t st) {
+    ndq_spinor d = {const_cast<void*>(src), NDQ_F64, NDQ_FULL, 1};
+    const SpinorView lay = flat_view(g, &d);
+    const int64_t vb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
+    const dim3 grid(nblocks(g->volume), (k + 1) / 2);
+    hipLaunchKernelGGL(k_rotate, grid, dim3(kBlock), 0, st, static_cast<const char*>(src), nsrc, Y, k,
+                       static_cast<char*>(dst), vb, lay, (int32_t)g->volume);
     NDQ_HIP(hipGetLastError());
     return NDQ_OK;
 }

@@ -1,0 +1,357 @@
+// Low modes of Q in FP64 on the GPU (Sec. 2.3): the space V of the l lowest
+// modes, the Rayleigh-Ritz vectors u_k in V with P Q u_k = nu_k u_k, their
+// residues rho_k = |(Q - nu_k) u_k| (Eq. 8), kappa_+- (Eq. 9) and the projector
+// bound of Eq. 10.
+//
+// V is found by thick-restart Lanczos (Wu & Simon) on B = T_d(A~), a Chebyshev
+// polynomial of A = Q^2 mapped from [a, lam_max^2] onto [-1, 1]: the low end of
+// the spectrum (below the cutoff a) becomes the dominant part of B's spectrum.
+// Every Lanczos vector is orthogonalised twice against the whole basis
+// (classical Gram-Schmidt, FP64).  The cutoff a comes from a short plain
+// Lanczos run on A (its Ritz values bound the eigenvalues from above).  After
+// each restart cycle the kept B-Ritz vectors are checked by Rayleigh-Ritz with
+// Q itself; the cycle stops once every returned rho_k <= tol * lam_max.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <complex>
+#include <numeric>
+#include <vector>
+
+#include "ndq_eig.h"
+#include "ndq_solver.h"
+
+namespace ndq {
+namespace {
+
+using cd = std::complex<double>;
+
+struct LmCtx {
+    const ndq_geom* g;
+    const ndq_gauge* U;
+    double m;
+    hipStream_t st;
+    int64_t vb;              // bytes per FP64 full spinor
+    char *VA, *VB, *W, *QU;
+    ndq_spinor X0, X1, S;
+    double *partials, *dots, *Ydev, *coef, *scal;
+    int64_t qcount = 0;
+
+    ndq_spinor vec(char* base, int i) const { return ndq_spinor{base + (int64_t)i * vb, NDQ_F64, NDQ_FULL, 1}; }
+
+    int qapply(const ndq_spinor* in, const ndq_spinor* out, double c0, int nv = 0, const ndq_spinor* const* v = nullptr,
+               const Coef* cv = nullptr) {
+        qcount += 1;
+        return q_combo(g, U, m, in, out, Coef{c0, nullptr}, nv, v, cv, nullptr, st);
+    }
+    int copy(const ndq_spinor* dst, const ndq_spinor* src, double c = 1.0) {
+        const ndq_spinor* v[1] = {src};
+        const Coef cc[1] = {Coef{c, nullptr}};
+        return lincomb(g, NDQ_F64, dst, 1, v, cc, nullptr, nullptr, st);
+    }
+    int norm2(const ndq_spinor* x, double* out) {
+        int rc = dot(g, x, nullptr, partials, scal, st);
+        if (rc) return rc;
+        NDQ_HIP(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, st));
+        NDQ_HIP(hipStreamSynchronize(st));
+        return NDQ_OK;
+    }
+    // host h[k] = <V_k, x>, k < n
+    int dots_to_host(char* base, int n, const ndq_spinor* x, std::vector<cd>& h) {
+        int rc = mode_dots(g, base, n, x, partials, dots, st);
+        if (rc) return rc;
+        h.resize(n);
+        NDQ_HIP(hipMemcpyAsync(h.data(), dots, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, st));
+        NDQ_HIP(hipStreamSynchronize(st));
+        return NDQ_OK;
+    }
+    // x -= sum_k h[k] V_k
+    int subtract(char* base, int n, const std::vector<cd>& h, const ndq_spinor* x) {
+        std::vector<cd> neg(n);
+        for (int k = 0; k < n; ++k) neg[k] = -h[k];
+        NDQ_HIP(hipMemcpyAsync(coef, neg.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice, st));
+        return mode_update(g, base, n, coef, x, x, st);
+    }
+};
+
+// out = A v = Q Q v
+int apply_A(LmCtx& c, const ndq_spinor* v, const ndq_spinor* out) {
+    int rc = c.qapply(v, &c.S, 1.0);
+    if (!rc) rc = c.qapply(&c.S, out, 1.0);
+    return rc;
+}
+
+// out = T_d(A~) v, A~ = (2A - (a+b))/(b-a); three-term recurrence, two Q per degree
+int apply_filter(LmCtx& c, const ndq_spinor* v, const ndq_spinor* out, double a, double b, int d) {
+    const double c1 = 2.0 / (b - a), c2 = -(a + b) / (b - a);
+    int rc;
+    ndq_spinor* tp = &c.X0;   // T_{k-1}
+    ndq_spinor* tc = &c.X1;   // T_k
+    if ((rc = c.copy(tp, v))) return rc;
+    if ((rc = c.qapply(v, &c.S, 1.0))) return rc;
+    {
+        const ndq_spinor* vv[1] = {v};
+        const Coef cv[1] = {Coef{c2, nullptr}};
+        if ((rc = c.qapply(&c.S, tc, c1, 1, vv, cv))) return rc;
+    }
+    for (int k = 2; k <= d; ++k) {
+        if ((rc = c.qapply(tc, &c.S, 1.0))) return rc;
+        const ndq_spinor* vv[2] = {tc, tp};
+        const Coef cv[2] = {Coef{2.0 * c2, nullptr}, Coef{-1.0, nullptr}};
+        if ((rc = c.qapply(&c.S, tp, 2.0 * c1, 2, vv, cv))) return rc;   // T_{k+1} into T_{k-1}'s buffer
+        std::swap(tp, tc);
+    }
+    return c.copy(out, tc);
+}
+
+// Lanczos steps j = j0 .. m-1 on the basis block `base` (m+1 vectors), recording
+// the projected matrix T (column j: <V_i, B V_j> for i <= j+1).  op: 0 = A, 1 = filter.
+int lanczos_steps(LmCtx& c, char* base, int j0, int m, std::vector<cd>& T, int op, double a, double b, int d) {
+    int rc;
+    std::vector<cd> h, h2;
+    for (int j = j0; j < m; ++j) {
+        const ndq_spinor vj = c.vec(base, j), w = c.vec(base, j + 1);
+        rc = op == 0 ? apply_A(c, &vj, &w) : apply_filter(c, &vj, &w, a, b, d);
+        if (rc) return rc;
+        if ((rc = c.dots_to_host(base, j + 1, &w, h))) return rc;
+        if ((rc = c.subtract(base, j + 1, h, &w))) return rc;
+        if ((rc = c.dots_to_host(base, j + 1, &w, h2))) return rc;
+        if ((rc = c.subtract(base, j + 1, h2, &w))) return rc;
+        double b2;
+        if ((rc = c.norm2(&w, &b2))) return rc;
+        const double beta = sqrt(b2);
+        if (!isfinite(beta)) return fail(NDQ_ENAN, "low modes: NaN in the Lanczos recurrence");
+        for (int i = 0; i <= j; ++i) T[(size_t)i * m + j] = h[i] + h2[i];
+        if (j + 1 < m) T[(size_t)(j + 1) * m + j] = beta;
+        if (beta == 0.0) return fail(NDQ_ENOCONV, "low modes: invariant subspace reached (beta = 0)");
+        if ((rc = c.copy(&w, &w, 1.0 / beta))) return rc;
+    }
+    return NDQ_OK;
+}
+
+// Hermitian completion of T from its upper triangle, eigen-decomposition.
+void eig_T(const std::vector<cd>& T, int m, std::vector<double>& w, std::vector<cd>& z) {
+    std::vector<cd> a((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) a[(size_t)i * m + j] = i <= j ? T[(size_t)i * m + j] : std::conj(T[(size_t)j * m + i]);
+    for (int i = 0; i < m; ++i) a[(size_t)i * m + i] = a[(size_t)i * m + i].real();
+    hermitian_eig(m, a, w, z);
+}
+
+}  // namespace
+}  // namespace ndq
+
+using namespace ndq;
+
+extern "C" {
+
+size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params* p) {
+    if (!g || !p || p->nev < 1 || p->basis < 2) return 0;
+    const size_t vb = (size_t)spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
+    const int m = p->basis, nkeep = p->nev + std::max(p->nextra, 1);
+    Arena ar{nullptr, 0};
+    ar.take(vb * (m + 1));
+    ar.take(vb * (m + 1));
+    ar.take(vb * nkeep);
+    ar.take(vb * p->nev);
+    for (int i = 0; i < 3; ++i) ar.take(vb);
+    ar.take(partials_capacity(g, 2 * NDQ_MAX_MODES));
+    ar.take(2 * NDQ_MAX_MODES * sizeof(double));
+    ar.take((size_t)2 * (m + 1) * (m + 1) * sizeof(double));
+    ar.take(2 * NDQ_MAX_MODES * sizeof(double));
+    ar.take(64 * sizeof(double));
+    return ar.used + 256;
+}
+
+int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double lam_max, const ndq_lowmode_params* p,
+                         const ndq_spinor* start, void* d_modes, double* nu, double* rho, ndq_lowmode_info* info,
+                         void* ws, size_t ws_bytes, void* stream) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!g || !p || !d_modes || !nu || !rho) return fail(NDQ_EINVAL, "ndq_lowmodes_compute: NULL argument");
+    int rc = check_gauge(U);
+    if (!rc) rc = check_spinor(g, start, NDQ_FULL, "ndq_lowmodes_compute start");
+    if (rc) return rc;
+    if (U->prec != NDQ_F64 || start->prec != NDQ_F64) return fail(NDQ_EPREC, "low modes: FP64 links and start vector");
+    const int nev = p->nev, nkeep = nev + std::max(p->nextra, 1), mb = p->basis;
+    if (nev < 1 || mb > NDQ_MAX_MODES - 1 || mb < nkeep + 2)
+        return fail(NDQ_EINVAL, "low modes: need 1 <= nev, nev + nextra + 2 <= basis <= %d", NDQ_MAX_MODES - 1);
+    if (!(lam_max > 0)) return fail(NDQ_EINVAL, "low modes: lam_max must be positive");
+    LmCtx c;
+    c.g = g;
+    c.U = U;
+    c.m = m;
+    c.st = as_stream(stream);
+    c.vb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
+    Arena ar{static_cast<char*>(ws), ws_bytes};
+    c.VA = static_cast<char*>(ar.take(c.vb * (mb + 1)));
+    c.VB = static_cast<char*>(ar.take(c.vb * (mb + 1)));
+    c.W = static_cast<char*>(ar.take(c.vb * nkeep));
+    c.QU = static_cast<char*>(ar.take(c.vb * nev));
+    c.X0 = ws_spinor(ar, g, NDQ_F64);
+    c.X1 = ws_spinor(ar, g, NDQ_F64);
+    c.S = ws_spinor(ar, g, NDQ_F64);
+    c.partials = static_cast<double*>(ar.take(partials_capacity(g, 2 * NDQ_MAX_MODES)));
+    c.dots = static_cast<double*>(ar.take(2 * NDQ_MAX_MODES * sizeof(double)));
+    c.Ydev = static_cast<double*>(ar.take((size_t)2 * (mb + 1) * (mb + 1) * sizeof(double)));
+    c.coef = static_cast<double*>(ar.take(2 * NDQ_MAX_MODES * sizeof(double)));
+    c.scal = static_cast<double*>(ar.take(64 * sizeof(double)));
+    if (ar.overflow) return fail(NDQ_ENOMEM, "low modes: workspace too small (need %zu bytes)", ar.used);
+    const double b = lam_max * lam_max;
+
+    // v0 = start / |start|
+    double s2;
+    {
+        const ndq_spinor v0 = c.vec(c.VA, 0);
+        if ((rc = c.norm2(start, &s2))) return rc;
+        if (!(s2 > 0) || !isfinite(s2)) return fail(NDQ_EINVAL, "low modes: zero or non-finite start vector");
+        if ((rc = c.copy(&v0, start, 1.0 / sqrt(s2)))) return rc;
+    }
+
+    // cutoff a and degree d from a plain Lanczos run on A = Q^2
+    double a = p->cheb_lo;
+    int d = p->cheb_degree;
+    if (!(a > 0) || d <= 0) {
+        const int m0 = mb;
+        std::vector<cd> T((size_t)m0 * m0, 0.0);
+        if ((rc = lanczos_steps(c, c.VA, 0, m0, T, 0, 0, 0, 0))) return rc;
+        std::vector<double> th;
+        std::vector<cd> z;
+        eig_T(T, m0, th, z);
+        if (!(a > 0)) a = th[std::min(nkeep, m0 - 1)];
+        if (d <= 0) {
+            const double lw = th[nev - 1];
+            const double x = 1.0 + 2.0 * (a - lw) / (b - a);
+            const double grow = x > 1.0 ? acosh(x) : 0.0;
+            d = grow > 0 ? (int)ceil(log(1e4) / grow) : 600;
+            d = std::min(600, std::max(16, d + (d & 1)));
+        }
+        // restart the filtered run from the original start vector
+        const ndq_spinor v0 = c.vec(c.VA, 0);
+        if ((rc = c.copy(&v0, start, 1.0 / sqrt(s2)))) return rc;
+    }
+    if (!(a > 0 && a < b)) return fail(NDQ_EINVAL, "low modes: filter cutoff %g outside (0, lam_max^2)", a);
+
+    std::vector<cd> T((size_t)mb * mb, 0.0);
+    int j0 = 0;
+    int restarts = 0;
+    const int max_restarts = p->max_restarts > 0 ? p->max_restarts : 50;
+    const double tol = p->tol > 0 ? p->tol : 1e-10;
+    std::vector<double> nu_sel(nev), rho_sel(nev);
+    double lam_next = 0.0, max_rho = 0.0;
+    bool converged = false;
+    for (;;) {
+        if ((rc = lanczos_steps(c, c.VA, j0, mb, T, 1, a, b, d))) return rc;
+        std::vector<double> th;
+        std::vector<cd> z;
+        eig_T(T, mb, th, z);
+        // keep the nkeep largest B-Ritz pairs (descending)
+        std::vector<cd> Y((size_t)mb * nkeep);
+        std::vector<double> thk(nkeep);
+        for (int j = 0; j < nkeep; ++j) {
+            const int col = mb - 1 - j;
+            thk[j] = th[col];
+            for (int i = 0; i < mb; ++i) Y[(size_t)i * nkeep + j] = z[(size_t)i * mb + col];
+        }
+        NDQ_HIP(hipMemcpyAsync(c.Ydev, Y.data(), sizeof(cd) * Y.size(), hipMemcpyHostToDevice, c.st));
+        if ((rc = rotate(g, c.VA, mb, c.Ydev, nkeep, c.VB, c.st))) return rc;
+        {
+            const ndq_spinor r = c.vec(c.VA, mb), dst = c.vec(c.VB, nkeep);
+            if ((rc = c.copy(&dst, &r))) return rc;
+        }
+        std::swap(c.VA, c.VB);
+        ++restarts;
+
+        // Rayleigh-Ritz of Q in span(VA[0..nkeep-1])
+        for (int i = 0; i < nkeep; ++i) {
+            const ndq_spinor vi = c.vec(c.VA, i), wi = c.vec(c.W, i);
+            if ((rc = c.qapply(&vi, &wi, 1.0))) return rc;
+        }
+        std::vector<cd> M((size_t)nkeep * nkeep), col;
+        for (int i = 0; i < nkeep; ++i) {
+            const ndq_spinor wi = c.vec(c.W, i);
+            if ((rc = c.dots_to_host(c.VA, nkeep, &wi, col))) return rc;
+            for (int k = 0; k < nkeep; ++k) M[(size_t)k * nkeep + i] = col[k];
+        }
+        for (int i = 0; i < nkeep; ++i)
+            for (int k = i + 1; k < nkeep; ++k) {
+                const cd avg = 0.5 * (M[(size_t)i * nkeep + k] + std::conj(M[(size_t)k * nkeep + i]));
+                M[(size_t)i * nkeep + k] = avg;
+                M[(size_t)k * nkeep + i] = std::conj(avg);
+            }
+        std::vector<double> nuv;
+        std::vector<cd> zq;
+        hermitian_eig(nkeep, M, nuv, zq);
+        std::vector<int> idx(nkeep);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::stable_sort(idx.begin(), idx.end(), [&](int i, int j) { return fabs(nuv[i]) < fabs(nuv[j]); });
+        std::vector<cd> Zs((size_t)nkeep * nev);
+        for (int j = 0; j < nev; ++j) {
+            nu_sel[j] = nuv[idx[j]];
+            for (int i = 0; i < nkeep; ++i) Zs[(size_t)i * nev + j] = zq[(size_t)i * nkeep + idx[j]];
+        }
+        lam_next = fabs(nuv[idx[nev]]);
+        NDQ_HIP(hipMemcpyAsync(c.Ydev, Zs.data(), sizeof(cd) * Zs.size(), hipMemcpyHostToDevice, c.st));
+        if ((rc = rotate(g, c.VA, nkeep, c.Ydev, nev, d_modes, c.st))) return rc;
+        if ((rc = rotate(g, c.W, nkeep, c.Ydev, nev, c.QU, c.st))) return rc;
+        max_rho = 0.0;
+        for (int k = 0; k < nev; ++k) {
+            const ndq_spinor qu = c.vec(c.QU, k);
+            const ndq_spinor uk = c.vec(static_cast<char*>(d_modes), k);
+            const ndq_spinor* v[2] = {&qu, &uk};
+            const Coef cf[2] = {Coef{1.0, nullptr}, Coef{-nu_sel[k], nullptr}};
+            if ((rc = lincomb(g, NDQ_F64, &c.X0, 2, v, cf, nullptr, nullptr, c.st))) return rc;
+            double r2;
+            if ((rc = c.norm2(&c.X0, &r2))) return rc;
+            rho_sel[k] = sqrt(r2);
+            max_rho = std::max(max_rho, rho_sel[k]);
+        }
+        if (max_rho <= tol * lam_max) {
+            converged = true;
+            break;
+        }
+        if (restarts >= max_restarts) break;
+        // thick restart: T = diag(theta) on the kept block, new column from V[nkeep]
+        std::fill(T.begin(), T.end(), cd(0.0, 0.0));
+        for (int j = 0; j < nkeep; ++j) T[(size_t)j * mb + j] = thk[j];
+        j0 = nkeep;
+    }
+    for (int k = 0; k < nev; ++k) {
+        nu[k] = nu_sel[k];
+        rho[k] = rho_sel[k];
+    }
+    if (info) {
+        memset(info, 0, sizeof(*info));
+        info->lam_next = lam_next;
+        // Eq. 9 with d_k = min(lam_next - |nu_k|, |nu_k| + min over opposite-sign |nu_j|)
+        double kp2 = 0.0, km2 = 0.0;
+        for (int k = 0; k < nev; ++k) {
+            double dk = lam_next - fabs(nu_sel[k]);
+            for (int j = 0; j < nev; ++j)
+                if ((nu_sel[j] > 0) != (nu_sel[k] > 0)) dk = std::min(dk, fabs(nu_sel[k]) + fabs(nu_sel[j]));
+            const double q = dk > 0 ? rho_sel[k] / dk : INFINITY;
+            (nu_sel[k] > 0 ? kp2 : km2) += q * q;
+        }
+        info->kappa_plus = sqrt(kp2);
+        info->kappa_minus = sqrt(km2);
+        auto bound = [](double k) {
+            const double q = k * (1.0 + 2.0 * k);
+            const double den = 1.0 - 2.0 * q;
+            return den > 0 ? q / den : INFINITY;
+        };
+        info->bound_plus = bound(info->kappa_plus);
+        info->bound_minus = bound(info->kappa_minus);
+        info->cheb_lo = a;
+        info->cheb_degree = d;
+        info->restarts = restarts;
+        info->q_applies = c.qcount;
+        info->max_rho = max_rho;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!converged)
+        return fail(NDQ_ENOCONV, "low modes: max rho %.3e > %.3e after %d restarts", max_rho, tol * lam_max, restarts);
+    return NDQ_OK;
+}
+
+}  // extern "C"

@@ -85,6 +85,10 @@ int mode_coef(const double* c, const double* d, const ModeSigns& sg, int use_sig
 int mode_update(const ndq_geom* g, const void* modes, int nev, const double* coef, const ndq_spinor* in,
                 const ndq_spinor* out, hipStream_t st);
 
+// dst_j = sum_i src_i Y[i][j] (j < k) over contiguous blocks of FP64 full spinors;
+// Y complex row-major [nsrc][k] in device memory; dst must not overlap src.
+int rotate(const ndq_geom* g, const void* src, int nsrc, const double* Y, int k, void* dst, hipStream_t st);
+
 // ---- multi-shift CG device state (blas.hip) ---------------------------------
 struct MsState {
     double b2;                        // |b|^2

@@ -58,6 +58,22 @@ class _Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class _LmParams(ctypes.Structure):
+    _fields_ = [("nev", ctypes.c_int32), ("nextra", ctypes.c_int32), ("basis", ctypes.c_int32),
+                ("cheb_degree", ctypes.c_int32), ("cheb_lo", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_restarts", ctypes.c_int32)]
+
+
+class _LmInfo(ctypes.Structure):
+    _fields_ = [("lam_next", ctypes.c_double), ("kappa_plus", ctypes.c_double), ("kappa_minus", ctypes.c_double),
+                ("bound_plus", ctypes.c_double), ("bound_minus", ctypes.c_double), ("cheb_lo", ctypes.c_double),
+                ("cheb_degree", ctypes.c_int32), ("restarts", ctypes.c_int32), ("q_applies", ctypes.c_int64),
+                ("max_rho", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _D = ctypes.c_double
@@ -89,6 +105,11 @@ _SIG = {
                             ctypes.POINTER(_Spinor), _P, ctypes.c_size_t, ctypes.POINTER(_Stats), _P]),
     "ndq_apply_DN": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Params), ctypes.POINTER(_Spinor),
                           ctypes.POINTER(_Spinor), _P, ctypes.c_size_t, ctypes.POINTER(_Stats), _P]),
+    "ndq_lowmodes_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(_LmParams)]),
+    "ndq_lowmodes_compute": (_I, [_P, ctypes.POINTER(_Gauge), _D, _D, ctypes.POINTER(_LmParams),
+                                  ctypes.POINTER(_Spinor), _P, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                  ctypes.POINTER(_LmInfo), _P, ctypes.c_size_t, _P]),
+    "ndq_host_eigh": (_I, [_I, _P, _P, _P]),
     "ndq_set_launch": (_I, [_I, _I]),
     "ndq_set_launch_for": (_I, [_I, _I, _I, _I, _I]),
 }
@@ -343,3 +364,38 @@ def apply_DN(geom: Geometry, U: GaugeField, ov: Overlap, inp: SpinorField, out: 
     _check(lib().ndq_apply_DN(geom.handle, ctypes.byref(U.desc), ctypes.byref(ov.p), ctypes.byref(inp.desc),
                               ctypes.byref(out.desc), _ptr(ws), ws.numel(), ctypes.byref(st), _stream(stream)))
     return st.as_dict()
+
+
+def lowmodes_compute(geom: Geometry, U: GaugeField, m: float, lam_max: float, start: SpinorField, nev: int,
+                     nextra: int = 8, basis: int = 0, cheb_degree: int = 0, cheb_lo: float = 0.0, tol: float = 1e-10,
+                     max_restarts: int = 50, stream=None):
+    """Low modes of Q: returns (modes SpinorField (F64, FULL, nrhs=nev), nu, rho, info dict)."""
+    import numpy as np
+    basis = basis or min(63, nev + nextra + max(12, nev))
+    p = _LmParams(nev, nextra, basis, cheb_degree, cheb_lo, tol, max_restarts)
+    nbytes = int(lib().ndq_lowmodes_workspace_bytes(geom.handle, ctypes.byref(p)))
+    if nbytes == 0:
+        raise NdqError(-1, "bad low-mode parameters")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    modes = SpinorField(geom, F64, FULL, nev)
+    nu = np.zeros(nev)
+    rho = np.zeros(nev)
+    info = _LmInfo()
+    rc = lib().ndq_lowmodes_compute(geom.handle, ctypes.byref(U.desc), float(m), float(lam_max), ctypes.byref(p),
+                                    ctypes.byref(start.desc), _ptr(modes.buf),
+                                    nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(info),
+                                    _ptr(ws), nbytes, _stream(stream))
+    _check(rc)
+    return modes, nu, rho, info.as_dict()
+
+
+def host_eigh(a):
+    """The library's host Hermitian eigensolver (for tests): returns (w, z)."""
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.complex128).copy()
+    n = a.shape[0]
+    w = np.zeros(n)
+    z = np.zeros((n, n), dtype=np.complex128)
+    _check(lib().ndq_host_eigh(n, a.ctypes.data, w.ctypes.data, z.ctypes.data))
+    return w, z

@@ -129,3 +129,15 @@ def test_approx_validation(ndq):
     a = ndq.Approx.from_coeffs(ndq.MINMAX_POLY, [1.0, 0.5, 0.25], lo=0.01, delta=0.1)
     assert a.n == 2 and abs(a.delta - 0.1) < 1e-15
     assert np.allclose(a.coeffs()[0], [1.0, 0.5, 0.25])
+
+
+@pytest.mark.parametrize("n", [1, 3, 17, 64])
+def test_host_eigh(ndq, n):
+    """The library's host Hermitian eigensolver against numpy's LAPACK eigh."""
+    rng = np.random.default_rng(n)
+    a = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    a = a + a.conj().T
+    w, z = ndq.host_eigh(a)
+    assert np.allclose(w, np.linalg.eigvalsh(a), atol=1e-12 * np.abs(w).max())
+    assert np.abs(a @ z - z * w).max() < 1e-12 * np.abs(w).max()
+    assert np.abs(z.conj().T @ z - np.eye(n)).max() < 1e-12

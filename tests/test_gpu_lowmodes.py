@@ -1,0 +1,98 @@
+"""GPU low-mode solver (Sec. 2.3) against dense diagonalisation and the oracle.
+
+* 4^4 random links, l = 8: eigenvalues vs the dense spectrum of Q, residues
+  rho_k recomputed by the oracle, orthonormality, the Eq. 10 bound against the
+  true projector deviation, and sign(Q) with these modes vs the oracle's closed
+  form with exact modes.
+* 8^4 random links, l = 12: residues recomputed by the oracle's stencil.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import approx, dirac, geometry, lowmodes, sign
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1010_5636_amd as ndq  # noqa: E402
+
+M = -1.4
+LMAX = 6.6
+
+
+def cu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def run(dims, u, nev, nextra=8, tol=1e-11, basis=0):
+    g = ndq.Geometry(dims)
+    U = ndq.GaugeField.pack(g, cu(u), ndq.F64, 18)
+    v = geometry.volume(dims)
+    start = ndq.SpinorField.pack(g, cu(synthetic.start_vector(v)), ndq.F64, ndq.FULL)
+    modes, nu, rho, info = ndq.lowmodes_compute(g, U, M, LMAX, start, nev, nextra=nextra, tol=tol, basis=basis)
+    return g, U, modes, nu, rho, info
+
+
+@pytest.fixture(scope="module")
+def dense4():
+    u = synthetic.gauge_field((4, 4, 4, 4))
+    q = dirac.dense_Q(u, M, (4, 4, 4, 4))
+    lam, w = np.linalg.eigh(q)
+    return {"u": u, "q": q, "eig": (lam, w), "order": np.argsort(np.abs(lam), kind="stable")}
+
+
+def test_lowmodes_random_4c4(dense4):
+    nev = 8
+    g, U, modes, nu, rho, info = run((4, 4, 4, 4), dense4["u"], nev)
+    lam = dense4["eig"][0][dense4["order"]]
+    assert np.allclose(np.sort(nu), np.sort(lam[:nev]), atol=1e-10), (nu, lam[:nev + 2])
+    assert np.all(rho <= 1e-11 * LMAX)
+    um = modes.unpack().cpu().numpy().reshape(nev, -1)
+    assert np.abs(um.conj() @ um.T - np.eye(nev)).max() < 1e-12
+    # rho_k recomputed with the oracle's stencil
+    qu = dirac.apply_Q(dense4["u"], um.reshape(nev, 256, 4, 3), M, (4, 4, 4, 4)).reshape(nev, -1)
+    rho_o = np.linalg.norm(qu - nu[:, None] * um, axis=1)
+    assert np.allclose(rho, rho_o, rtol=1e-3, atol=1e-13)
+    assert abs(info["lam_next"] - abs(lam[nev])) < 1e-6
+    # Eq. 10 against the true projector deviation
+    nu_ex, m_ex = lowmodes.dense_lowmodes(dense4["q"], nev, eig=dense4["eig"])
+    for sgn, bound in ((1, info["bound_plus"]), (-1, info["bound_minus"])):
+        pe = m_ex[np.sign(nu_ex) == sgn]
+        pg = um[np.sign(nu) == sgn]
+        dev = np.linalg.norm(pg.T @ pg.conj() - pe.T @ pe.conj(), 2)
+        assert dev <= bound + 1e-12
+
+
+def test_sign_with_computed_modes(dense4):
+    nev = 8
+    g, U, modes, nu, rho, info = run((4, 4, 4, 4), dense4["u"], nev)
+    k = abs(dense4["eig"][0][dense4["order"][nev]]) / LMAX
+    ap, ref_ap = ndq.Approx(ndq.ZOLOTAREV, k, 10), approx.zolotarev(k, 10)
+    psi = synthetic.spinor(256, seed=17)
+    ov = ndq.Overlap(g, M, ap, LMAX, modes=modes, nu=nu, tol=1e-13)
+    x = ndq.SpinorField.pack(g, cu(psi), ndq.F64, ndq.FULL)
+    y = x.like()
+    ndq.apply_sign(g, U, ov, x, y)
+    got = y.unpack().cpu().numpy().ravel()
+    ref = sign.dense_sign_approx(dense4["q"], ref_ap, LMAX, n_low=nev, eig=dense4["eig"]) @ psi.ravel()
+    assert np.linalg.norm(got - ref) <= 1e-8 * np.linalg.norm(psi)
+
+
+def test_lowmodes_8c4_residuals():
+    dims = (8, 8, 8, 8)
+    u = synthetic.gauge_field(dims, seed=5)
+    nev = 12
+    g, U, modes, nu, rho, info = run(dims, u, nev, tol=1e-10)
+    v = geometry.volume(dims)
+    um = modes.unpack().cpu().numpy()
+    qu = dirac.apply_Q(u, um, M, dims).reshape(nev, -1)
+    rho_o = np.linalg.norm(qu - nu[:, None] * um.reshape(nev, -1), axis=1)
+    assert np.all(rho_o <= 1e-10 * LMAX * 1.01)
+    gram = um.reshape(nev, -1).conj() @ um.reshape(nev, -1).T
+    assert np.abs(gram - np.eye(nev)).max() < 1e-12
+    assert np.all(np.abs(nu) <= info["lam_next"] + 1e-12)
+    assert np.all(np.diff(np.abs(nu)) >= -1e-14)
