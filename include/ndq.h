@@ -215,6 +215,30 @@ int ndq_apply_DN(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params
                  const ndq_spinor* in, const ndq_spinor* out, void* ws, size_t ws_bytes,
                  ndq_stats* stats, void* stream);
 
+/* ---- solving D_N^m x = b --------------------------------------------------- */
+typedef struct {
+    double tol;           /* target true residual |b - D x| / |b|, D the FP64 operator of p64 */
+    int32_t max_outer;    /* defect-correction steps (<= 0: 20)                             */
+    int32_t max_inner;    /* CG iterations per inner solve (<= 0: no limit)                 */
+    double inner_tol;     /* inner relative residual (<= 0: 1e-5 mixed, tol/2 plain FP64)   */
+    int32_t inner_prec;   /* NDQ_F64: plain FP64 solve; NDQ_F32 / NDQ_F16: mixed precision  */
+} ndq_solve_params;
+
+size_t ndq_solve_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p64, const ndq_overlap_params* plo,
+                                 const ndq_solve_params* sp);
+
+/* x = (D_N^m)^{-1} b (Eq. 4 with the massive form of Eq. 12).  FP64 defect
+ * correction: r = b - D x with the FP64 operator (U64, p64); while |r| > tol |b|,
+ * solve D e = r/|r| by CG on the normal equations (D^H = gamma5 D gamma5) in the
+ * inner precision (U_lo and p_lo: F32 arithmetic on F32 or F16 storage, with their
+ * own approximant; or FP64 with U64, p64 for the plain solve) and set x += |r| e.
+ * b, x: F64 NDQ_FULL, nrhs 1; x holds the initial guess on entry.  Synchronises
+ * `stream`.  stats: outer steps, inner CG iterations, Q applications, final true
+ * relative residual.  Errors: NDQ_ENOCONV, NDQ_ENOMEM, NDQ_ENAN, NDQ_EPREC. */
+int ndq_solve_DN(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* U_lo, const ndq_overlap_params* p64,
+                 const ndq_overlap_params* p_lo, const ndq_solve_params* sp, const ndq_spinor* b,
+                 const ndq_spinor* x, void* ws, size_t ws_bytes, ndq_stats* stats, void* stream);
+
 /* ---- low modes of Q (FP64) ----------------------------------------------- */
 typedef struct {
     int32_t nev;          /* number l of low modes of Q to return (>= 1)                      */
@@ -236,7 +260,9 @@ typedef struct {
     int32_t cheb_degree;  /* filter degree used                                               */
     int32_t restarts;
     int64_t q_applies;
-    double max_rho;
+    double max_rho;       /* largest rho_k of the returned modes                             */
+    double rho_next;      /* residue of the next Ritz pair: some eigenvalue lies within
+                             rho_next of +-lam_next, so lam_next - rho_next bounds it below  */
     double seconds;
 } ndq_lowmode_info;
 
@@ -248,7 +274,9 @@ size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params*
  * (Eq. 8) and kappa_+- (Eq. 9), bound (Eq. 10).
  *   U: F64 links;  start: F64 NDQ_FULL spinor (nonzero);  d_modes: out, nev packed F64
  *   NDQ_FULL spinors back to back (orthonormal);  nu, rho: host arrays of nev, sorted by
- *   |nu| ascending.  Synchronises `stream`.  Errors: NDQ_ENOCONV (tol not reached; the
+ *   |nu| ascending.  The (nev+1)-th Ritz pair (|nu| = lam_next) is converged to
+ *   max(tol, 1e-6) * lam_max.
+ *   Synchronises `stream`.  Errors: NDQ_ENOCONV (tol not reached; the
  *   best modes found are still written), NDQ_ENOMEM, NDQ_EPREC, NDQ_ENAN. */
 int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double lam_max,
                          const ndq_lowmode_params* p, const ndq_spinor* start, void* d_modes, double* nu,

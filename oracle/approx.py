@@ -209,6 +209,9 @@ def _alternating_subset(pts: np.ndarray, vals: np.ndarray, count: int):
     return np.array(p), np.array(v)
 
 
+ROUNDING_FLOOR = 1e-13   # max |h| at which double-precision evaluation noise dominates
+
+
 def _golden_refine(f, lo: np.ndarray, hi: np.ndarray, sgn: np.ndarray, iters: int = 60):
     """Golden-section search of sgn*f for a maximum inside each bracket [lo, hi],
     all brackets at once."""
@@ -246,6 +249,7 @@ def minimax_polynomial(eps: float, n: int, tol: float = 1e-7, max_iter: int = 60
     theta_ref = np.pi * np.arange(m)[::-1] / (m - 1)
     yref = y_of_theta(theta_ref)
     poly = None
+    best = None
     for _ in range(max_iter):
         zr = (2.0 * yref - 1.0 - eps) / (1.0 - eps)
         a = np.empty((m, m))
@@ -269,13 +273,18 @@ def minimax_polynomial(eps: float, n: int, tol: float = 1e-7, max_iter: int = 60
         pts, vals = pts[order], vals[order]
         emax = float(np.max(np.abs(vals)))
         poly.delta = emax
-        if emax - lev <= tol * emax:
+        # Eq. 6 asks for the smallest max |h|: keep the best iterate.  Once the
+        # error reaches the rounding floor of double precision the extrema are
+        # rounding noise and further exchanges only degrade the reference.
+        if best is None or emax < best.delta:
+            best = poly
+        if emax - lev <= tol * emax or emax <= ROUNDING_FLOOR:
             break
         sel_t, _ = _alternating_subset(pts, vals, m)
         if len(sel_t) < m:
             break
         yref = y_of_theta(sel_t)
-    return poly
+    return best
 
 
 def eval_forward_recurrence(poly: Polynomial, apply_z, psi: np.ndarray) -> np.ndarray:

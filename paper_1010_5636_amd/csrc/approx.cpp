@@ -171,8 +171,8 @@ int make_minmax(double eps, int n, ndq::Approx* ap) {
     auto y_of = [&](double th) { return 0.5 * ((1.0 - eps) * cos(th) + 1.0 + eps); };
     std::vector<double> theta(m);
     for (int i = 0; i < m; ++i) theta[i] = M_PI * (double)(m - 1 - i) / (double)(m - 1);  // y ascending
-    std::vector<double> c(n + 1, 0.0);
-    double delta = 1.0;
+    std::vector<double> c(n + 1, 0.0), best_c;
+    double delta = 1.0, best_delta = INFINITY;
     for (int iter = 0; iter < 80; ++iter) {
         // sqrt(y_i) P(y_i) + (-1)^i E = 1
         std::vector<double> A((size_t)m * m), rhs(m, 1.0);
@@ -223,7 +223,14 @@ int make_minmax(double eps, int n, ndq::Approx* ap) {
             }
         }
         delta = emax;
-        if (emax - level <= 1e-7 * emax) break;
+        // keep the iterate with the smallest max error (the quantity minimised);
+        // at ~1e-13 the error curve is double-precision rounding noise and further
+        // exchanges would only pick noise extrema
+        if (emax < best_delta) {
+            best_delta = emax;
+            best_c = c;
+        }
+        if (emax - level <= 1e-7 * emax || emax <= 1e-13) break;
         while ((int)pts.size() > m) {
             if (fabs(vals.front()) < fabs(vals.back())) {
                 pts.erase(pts.begin());
@@ -236,9 +243,10 @@ int make_minmax(double eps, int n, ndq::Approx* ap) {
         if ((int)pts.size() < m) break;
         theta = pts;
     }
-    ap->a = c;
+    (void)delta;
+    ap->a = best_c.empty() ? c : best_c;
     ap->b.clear();
-    ap->delta = delta;
+    ap->delta = best_c.empty() ? delta : best_delta;
     return NDQ_OK;
 }
 

@@ -10,7 +10,8 @@
 // (classical Gram-Schmidt, FP64).  The cutoff a comes from a short plain
 // Lanczos run on A (its Ritz values bound the eigenvalues from above).  After
 // each restart cycle the kept B-Ritz vectors are checked by Rayleigh-Ritz with
-// Q itself; the cycle stops once every returned rho_k <= tol * lam_max.
+// Q itself; the cycle stops once every returned rho_k <= tol * lam_max and the
+// next Ritz pair (whose |nu| is reported as lam_next) has rho <= max(tol, 1e-6) * lam_max.
 #include <math.h>
 #include <string.h>
 
@@ -34,7 +35,7 @@ struct LmCtx {
     double m;
     hipStream_t st;
     int64_t vb;              // bytes per FP64 full spinor
-    char *VA, *VB, *W, *QU;
+    char *VA, *VB, *W, *QU, *UU;
     ndq_spinor X0, X1, S;
     double *partials, *dots, *Ydev, *coef, *scal;
     int64_t qcount = 0;
@@ -155,7 +156,8 @@ size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params*
     ar.take(vb * (m + 1));
     ar.take(vb * (m + 1));
     ar.take(vb * nkeep);
-    ar.take(vb * p->nev);
+    ar.take(vb * (p->nev + 1));
+    ar.take(vb * (p->nev + 1));
     for (int i = 0; i < 3; ++i) ar.take(vb);
     ar.take(partials_capacity(g, 2 * NDQ_MAX_MODES));
     ar.take(2 * NDQ_MAX_MODES * sizeof(double));
@@ -188,7 +190,8 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     c.VA = static_cast<char*>(ar.take(c.vb * (mb + 1)));
     c.VB = static_cast<char*>(ar.take(c.vb * (mb + 1)));
     c.W = static_cast<char*>(ar.take(c.vb * nkeep));
-    c.QU = static_cast<char*>(ar.take(c.vb * nev));
+    c.QU = static_cast<char*>(ar.take(c.vb * (nev + 1)));
+    c.UU = static_cast<char*>(ar.take(c.vb * (nev + 1)));
     c.X0 = ws_spinor(ar, g, NDQ_F64);
     c.X1 = ws_spinor(ar, g, NDQ_F64);
     c.S = ws_spinor(ar, g, NDQ_F64);
@@ -239,7 +242,8 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     const int max_restarts = p->max_restarts > 0 ? p->max_restarts : 50;
     const double tol = p->tol > 0 ? p->tol : 1e-10;
     std::vector<double> nu_sel(nev), rho_sel(nev);
-    double lam_next = 0.0, max_rho = 0.0;
+    double lam_next = 0.0, max_rho = 0.0, rho_next = 0.0;
+    const double guard_tol = std::max(tol, 1e-6);
     bool converged = false;
     for (;;) {
         if ((rc = lanczos_steps(c, c.VA, j0, mb, T, 1, a, b, d))) return rc;
@@ -286,28 +290,41 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
         std::vector<int> idx(nkeep);
         std::iota(idx.begin(), idx.end(), 0);
         std::stable_sort(idx.begin(), idx.end(), [&](int i, int j) { return fabs(nuv[i]) < fabs(nuv[j]); });
-        std::vector<cd> Zs((size_t)nkeep * nev);
-        for (int j = 0; j < nev; ++j) {
-            nu_sel[j] = nuv[idx[j]];
-            for (int i = 0; i < nkeep; ++i) Zs[(size_t)i * nev + j] = zq[(size_t)i * nkeep + idx[j]];
+        // the nev modes plus the next one (its eigenvalue is lam_next; it must be
+        // converged too, or an eigenvalue could hide between |nu_nev| and lam_next)
+        const int nsel = nev + 1;
+        std::vector<cd> Zs((size_t)nkeep * nsel);
+        std::vector<double> nu_all(nsel), rho_all(nsel);
+        for (int j = 0; j < nsel; ++j) {
+            nu_all[j] = nuv[idx[j]];
+            for (int i = 0; i < nkeep; ++i) Zs[(size_t)i * nsel + j] = zq[(size_t)i * nkeep + idx[j]];
         }
-        lam_next = fabs(nuv[idx[nev]]);
+        lam_next = fabs(nu_all[nev]);
         NDQ_HIP(hipMemcpyAsync(c.Ydev, Zs.data(), sizeof(cd) * Zs.size(), hipMemcpyHostToDevice, c.st));
-        if ((rc = rotate(g, c.VA, nkeep, c.Ydev, nev, d_modes, c.st))) return rc;
-        if ((rc = rotate(g, c.W, nkeep, c.Ydev, nev, c.QU, c.st))) return rc;
+        if ((rc = rotate(g, c.VA, nkeep, c.Ydev, nsel, c.UU, c.st))) return rc;
+        if ((rc = rotate(g, c.W, nkeep, c.Ydev, nsel, c.QU, c.st))) return rc;
         max_rho = 0.0;
-        for (int k = 0; k < nev; ++k) {
+        for (int k = 0; k < nsel; ++k) {
             const ndq_spinor qu = c.vec(c.QU, k);
-            const ndq_spinor uk = c.vec(static_cast<char*>(d_modes), k);
+            const ndq_spinor uk = c.vec(c.UU, k);
             const ndq_spinor* v[2] = {&qu, &uk};
-            const Coef cf[2] = {Coef{1.0, nullptr}, Coef{-nu_sel[k], nullptr}};
+            const Coef cf[2] = {Coef{1.0, nullptr}, Coef{-nu_all[k], nullptr}};
             if ((rc = lincomb(g, NDQ_F64, &c.X0, 2, v, cf, nullptr, nullptr, c.st))) return rc;
             double r2;
             if ((rc = c.norm2(&c.X0, &r2))) return rc;
-            rho_sel[k] = sqrt(r2);
-            max_rho = std::max(max_rho, rho_sel[k]);
+            rho_all[k] = sqrt(r2);
+            if (k < nev) max_rho = std::max(max_rho, rho_all[k]);
         }
-        if (max_rho <= tol * lam_max) {
+        for (int k = 0; k < nev; ++k) {
+            nu_sel[k] = nu_all[k];
+            rho_sel[k] = rho_all[k];
+        }
+        rho_next = rho_all[nev];
+        NDQ_HIP(hipMemcpyAsync(d_modes, c.UU, (size_t)c.vb * nev, hipMemcpyDeviceToDevice, c.st));
+        NDQ_HIP(hipStreamSynchronize(c.st));
+        // the returned modes to tol; the next pair only to guard_tol, enough for
+        // lam_next - rho_next to bound the next eigenvalue's modulus from below
+        if (max_rho <= tol * lam_max && rho_next <= guard_tol * lam_max) {
             converged = true;
             break;
         }
@@ -347,10 +364,12 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
         info->restarts = restarts;
         info->q_applies = c.qcount;
         info->max_rho = max_rho;
+        info->rho_next = rho_next;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     if (!converged)
-        return fail(NDQ_ENOCONV, "low modes: max rho %.3e > %.3e after %d restarts", max_rho, tol * lam_max, restarts);
+        return fail(NDQ_ENOCONV, "low modes: max rho %.3e (next %.3e) > %.3e after %d restarts", max_rho, rho_next,
+                    tol * lam_max, restarts);
     return NDQ_OK;
 }
 

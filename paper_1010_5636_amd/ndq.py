@@ -68,10 +68,15 @@ class _LmInfo(ctypes.Structure):
     _fields_ = [("lam_next", ctypes.c_double), ("kappa_plus", ctypes.c_double), ("kappa_minus", ctypes.c_double),
                 ("bound_plus", ctypes.c_double), ("bound_minus", ctypes.c_double), ("cheb_lo", ctypes.c_double),
                 ("cheb_degree", ctypes.c_int32), ("restarts", ctypes.c_int32), ("q_applies", ctypes.c_int64),
-                ("max_rho", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("max_rho", ctypes.c_double), ("rho_next", ctypes.c_double), ("seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class _SolveParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("inner_prec", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -110,6 +115,11 @@ _SIG = {
                                   ctypes.POINTER(_Spinor), _P, ctypes.POINTER(_D), ctypes.POINTER(_D),
                                   ctypes.POINTER(_LmInfo), _P, ctypes.c_size_t, _P]),
     "ndq_host_eigh": (_I, [_I, _P, _P, _P]),
+    "ndq_solve_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(_Params), ctypes.POINTER(_Params),
+                                                    ctypes.POINTER(_SolveParams)]),
+    "ndq_solve_DN": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Gauge), ctypes.POINTER(_Params),
+                          ctypes.POINTER(_Params), ctypes.POINTER(_SolveParams), ctypes.POINTER(_Spinor),
+                          ctypes.POINTER(_Spinor), _P, ctypes.c_size_t, ctypes.POINTER(_Stats), _P]),
     "ndq_set_launch": (_I, [_I, _I]),
     "ndq_set_launch_for": (_I, [_I, _I, _I, _I, _I]),
 }
@@ -399,3 +409,20 @@ def host_eigh(a):
     z = np.zeros((n, n), dtype=np.complex128)
     _check(lib().ndq_host_eigh(n, a.ctypes.data, w.ctypes.data, z.ctypes.data))
     return w, z
+
+
+def solve_DN(geom: Geometry, U64: GaugeField, ov64: Overlap, b: SpinorField, x: SpinorField, tol: float = 1e-10,
+             U_lo: GaugeField | None = None, ov_lo: Overlap | None = None, inner_prec: int = F64,
+             inner_tol: float = 0.0, max_outer: int = 20, max_inner: int = 0, stream=None) -> dict:
+    """x = (D_N^m)^{-1} b; x holds the initial guess (e.g. zeros) on entry."""
+    sp = _SolveParams(float(tol), int(max_outer), int(max_inner), float(inner_tol), int(inner_prec))
+    plo = ctypes.byref(ov_lo.p) if ov_lo is not None else None
+    n = int(lib().ndq_solve_workspace_bytes(geom.handle, ctypes.byref(ov64.p), plo, ctypes.byref(sp)))
+    if n == 0:
+        raise NdqError(-1, "bad solve parameters")
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    st = _Stats()
+    _check(lib().ndq_solve_DN(geom.handle, ctypes.byref(U64.desc), None if U_lo is None else ctypes.byref(U_lo.desc),
+                              ctypes.byref(ov64.p), plo, ctypes.byref(sp), ctypes.byref(b.desc), ctypes.byref(x.desc),
+                              _ptr(ws), n, ctypes.byref(st), _stream(stream)))
+    return st.as_dict()

@@ -141,3 +141,13 @@ def test_host_eigh(ndq, n):
     assert np.allclose(w, np.linalg.eigvalsh(a), atol=1e-12 * np.abs(w).max())
     assert np.abs(a @ z - z * w).max() < 1e-12 * np.abs(w).max()
     assert np.abs(z.conj().T @ z - np.eye(n)).max() < 1e-12
+
+
+def test_minmax_library_at_rounding_floor(ndq):
+    from oracle import approx
+    k, n = 0.0932, 260
+    a = ndq.Approx(ndq.MINMAX_POLY, k * k, n)
+    c, _ = a.coeffs()
+    ref = approx.minimax_polynomial(k * k, n)
+    assert a.delta < 1e-13
+    assert np.abs(c - ref.c).max() < 1e-12

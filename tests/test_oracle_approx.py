@@ -104,3 +104,12 @@ def test_zolotarev_error_decreases():
     d = [approx.zolotarev(0.0909, n).delta for n in (5, 6, 8, 10)]
     assert all(a > b for a, b in zip(d, d[1:]))
     assert d[-1] < 1e-10
+
+
+@pytest.mark.parametrize("k,n", [(0.0932, 260), (0.0932, 400)])
+def test_minimax_at_rounding_floor(k, n):
+    """Degrees whose optimum error is below double-precision noise: the result
+    must still approximate (regression: the exchange once chased noise extrema)."""
+    p = approx.minimax_polynomial(k * k, n)
+    y = np.linspace(k * k, 1.0, 200001)
+    assert np.abs(p.h(y)).max() < 1e-13
