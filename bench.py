@@ -92,6 +92,89 @@ def cpu_baseline(max_seconds=20.0):
                       f"({el:.1f} s, one thread)"}
 
 
+SOLVE_DIMS = (48, 24, 24, 24)
+SOLVE_MQ = 0.05
+SOLVE_NEV = 20
+LAM_MAX = 6.6
+
+
+def poly_for(ndq, eps, target):
+    """Smallest-degree minimax polynomial (library Remez) with delta <= target."""
+    n = max(8, int(0.8 * np.log(2.0 / target) / (2.0 * np.sqrt(eps))))
+    while True:
+        a = ndq.Approx(ndq.MINMAX_POLY, eps, n)
+        if a.delta <= target:
+            return a
+        n += max(4, n // 10)
+
+
+def solve_leg(log):
+    """D_N^m solves on the 24^3 x 48 lattice: mixed precision (F32 arithmetic on
+    F32 or F16 storage, FP64 defect correction) vs plain FP64, to a 1e-10 true
+    relative residual.  Setup (fields, 20 FP64 low modes, approximants) is timed
+    separately and excluded from solves/s."""
+    import torch
+    import synthetic
+    import paper_1010_5636_amd as ndq
+    dev = torch.device("cuda")
+    t0 = time.perf_counter()
+    g = ndq.Geometry(SOLVE_DIMS)
+    v = g.volume
+    u = torch.from_numpy(synthetic.gauge_field(SOLVE_DIMS)).to(dev)
+    U64 = ndq.GaugeField.pack(g, u, ndq.F64, 18)
+    U32 = ndq.GaugeField.pack(g, u, ndq.F32, 12)
+    U16 = ndq.GaugeField.pack(g, u, ndq.F16, 12)
+    del u
+    start = ndq.SpinorField.pack(g, torch.from_numpy(synthetic.start_vector(v)).to(dev), ndq.F64, ndq.FULL)
+    b = ndq.SpinorField.pack(g, torch.from_numpy(synthetic.spinor(v)).to(dev), ndq.F64, ndq.FULL)
+    torch.cuda.synchronize()
+    t_fields = time.perf_counter() - t0
+    log(f"solve leg: fields {t_fields:.1f} s")
+    t0 = time.perf_counter()
+    modes, nu, rho, info = ndq.lowmodes_compute(g, U64, M, LAM_MAX, start, SOLVE_NEV, tol=1e-11)
+    t_modes = time.perf_counter() - t0
+    log(f"solve leg: low modes {t_modes:.1f} s, {info['q_applies']} Q applies, lam_next {info['lam_next']:.5f}")
+    k = (info["lam_next"] - info["rho_next"]) / LAM_MAX
+    eps = k * k
+    t0 = time.perf_counter()
+    ap64 = poly_for(ndq, eps, 1e-12)
+    ap_lo = poly_for(ndq, eps, 1e-6)
+    t_approx = time.perf_counter() - t0
+    ov64 = ndq.Overlap(g, M, ap64, LAM_MAX, modes=modes, nu=nu, mq=SOLVE_MQ)
+    ov_lo = ndq.Overlap(g, M, ap_lo, LAM_MAX, modes=modes, nu=nu, mq=SOLVE_MQ)
+    out = {"workload": "D_N^m x = b, 24^3x48, m=-1.4, mq=0.05, 20 exact low modes (FP64 block Chebyshev-filtered subspace iteration), "
+                       "complex Gaussian b, true relative residual 1e-10 with the FP64 operator",
+           "dims": list(SOLVE_DIMS), "setup_s": {"fields": round(t_fields, 2), "lowmodes": round(t_modes, 2),
+                                                 "approximants": round(t_approx, 2)},
+           "lowmodes": {"nev": SOLVE_NEV, "nu_abs_min": float(np.abs(nu).min()), "nu_abs_max": float(np.abs(nu).max()),
+                        "lam_next": info["lam_next"], "max_rho": info["max_rho"], "kappa_plus": info["kappa_plus"],
+                        "kappa_minus": info["kappa_minus"], "q_applies": info["q_applies"],
+                        "restarts": info["restarts"], "cheb_degree": info["cheb_degree"]},
+           "approximant": {"kind": "minimax polynomial (Clenshaw)", "eps": eps, "degree_fp64": ap64.n,
+                           "delta_fp64": ap64.delta, "degree_inner": ap_lo.n, "delta_inner": ap_lo.delta}}
+    runs = {}
+    for name, prec, Ulo, ovlo, itol in (("mixed_f32", ndq.F32, U32, ov_lo, 0.0),
+                                        ("mixed_f16", ndq.F16, U16, ov_lo, 2e-3),
+                                        ("fp64", ndq.F64, None, None, 0.0)):
+        x = ndq.SpinorField(g, ndq.F64, ndq.FULL)
+        x.buf.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ndq.solve_DN(g, U64, ov64, b, x, tol=1e-10, U_lo=Ulo, ov_lo=ovlo, inner_prec=prec, inner_tol=itol,
+                          max_outer=30)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        runs[name] = {"seconds": round(el, 3), "solves_per_s": round(1.0 / el, 4), "residual": st["residual"],
+                      "outer": st["outer"], "inner_cg_iterations": st["inner"], "q_applies": st["q_applies"]}
+        log(f"solve leg: {name} {el:.2f} s, residual {st['residual']:.2e}, outer {st['outer']}, "
+            f"inner {st['inner']}, Q applies {st['q_applies']}")
+        del x
+    out["runs"] = runs
+    out["speedup_mixed_f32_vs_fp64"] = round(runs["fp64"]["seconds"] / runs["mixed_f32"]["seconds"], 3)
+    out["speedup_mixed_f16_vs_fp64"] = round(runs["fp64"]["seconds"] / runs["mixed_f16"]["seconds"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +186,7 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay the timed launches from a HIP graph")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run a device-to-device copy of BYTES bytes (counter calibration)")
+    ap.add_argument("--no-solve", action="store_true", help="skip the 24^3x48 D_N solve leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: multi-GPU runs are not part of this build "
@@ -233,6 +317,8 @@ def main():
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in r.items()}
                      for k, r in results.items()},
     }
+    if not args.no_solve:
+        out["dn_solve"] = solve_leg(lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -243,15 +243,20 @@ int ndq_solve_DN(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* U_lo,
 typedef struct {
     int32_t nev;          /* number l of low modes of Q to return (>= 1)                      */
     int32_t nextra;       /* extra Ritz vectors carried as a guard band (>= 1)                */
-    int32_t basis;        /* Lanczos basis size m, nev + nextra + 2 <= m <= 63                */
+    int32_t basis;        /* Lanczos basis size m, nev + nextra + 2 <= m <= 63 (Lanczos only)  */
     int32_t cheb_degree;  /* degree d of the Chebyshev filter (even); <= 0: automatic        */
     double cheb_lo;       /* filter cutoff a on Q^2; <= 0: from a plain Lanczos run           */
     double tol;           /* stop when every rho_k <= tol * lam_max                          */
-    int32_t max_restarts; /* restart cycles (<= 0: 50)                                        */
+    int32_t max_restarts; /* iterations / restart cycles (<= 0: 200 subspace, 100 Lanczos)     */
+    int32_t method;       /* NDQ_LM_SUBSPACE (block Chebyshev-filtered subspace iteration,
+                             adaptive filter) or NDQ_LM_LANCZOS (thick-restart Lanczos)       */
 } ndq_lowmode_params;
 
+enum { NDQ_LM_SUBSPACE = 0, NDQ_LM_LANCZOS = 1 };
+
 typedef struct {
-    double lam_next;      /* smallest |nu| of the Rayleigh-Ritz values not returned          */
+    double lam_next;      /* |Q u| of the guard vector u (the next Ritz vector after the
+                             nev returned, in the order of |Q u|^2)                          */
     double kappa_plus;    /* Eq. 9, with d_k = min(lam_next - |nu_k|, |nu_k| + min|nu_j| over */
     double kappa_minus;   /*   the returned nu_j of opposite sign)                             */
     double bound_plus;    /* Eq. 10: |P_+ - (P_+)_exact| <= kappa(1+2kappa)/(1-2kappa(1+2kappa)) */
@@ -261,21 +266,25 @@ typedef struct {
     int32_t restarts;
     int64_t q_applies;
     double max_rho;       /* largest rho_k of the returned modes                             */
-    double rho_next;      /* residue of the next Ritz pair: some eigenvalue lies within
-                             rho_next of +-lam_next, so lam_next - rho_next bounds it below  */
+    double rho_next;      /* from the guard residue r = |Q^2 u - lam_next^2 u|: Q has an
+                             eigenvalue with |lambda| >= lam_next - rho_next = sqrt(lam_next^2 - r) */
     double seconds;
 } ndq_lowmode_info;
 
 size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params* p);
 
-/* The nev eigenmodes of Q closest to zero (Sec. 2.3): thick-restart Lanczos on a
- * Chebyshev filter of Q^2 (FP64, full reorthogonalisation), then Rayleigh-Ritz of Q
- * in the converged space (P Q u_k = nu_k u_k), residues rho_k = |(Q - nu_k) u_k|
- * (Eq. 8) and kappa_+- (Eq. 9), bound (Eq. 10).
+/* The nev eigenmodes of Q closest to zero (Sec. 2.3): a Chebyshev filter of Q^2
+ * inside block subspace iteration or thick-restart Lanczos (FP64, CGS2
+ * orthogonalisation), Rayleigh-Ritz of Q in the space found (P Q u_k = nu_k u_k,
+ * nev + nextra <= 64), residues rho_k = |(Q - nu_k) u_k|
+ * (Eq. 8) and kappa_+- (Eq. 9), bound (Eq. 10).  Ritz pairs are ordered by
+ * |Q u|^2, the Rayleigh quotient of Q^2 (equal to nu^2 once converged), which
+ * keeps spurious near-zero Ritz values of the indefinite Q out of the result.
  *   U: F64 links;  start: F64 NDQ_FULL spinor (nonzero);  d_modes: out, nev packed F64
- *   NDQ_FULL spinors back to back (orthonormal);  nu, rho: host arrays of nev, sorted by
- *   |nu| ascending.  The (nev+1)-th Ritz pair (|nu| = lam_next) is converged to
- *   max(tol, 1e-6) * lam_max.
+ *   NDQ_FULL spinors back to back (orthonormal);  nu, rho: host arrays of nev, in
+ *   that order (|nu| ascending once converged).  Converged means every rho_k <=
+ *   tol * lam_max and the guard (the next Ritz vector) has a residue of Q^2 of at
+ *   most max(tol, 1e-6) * lam_max^2.
  *   Synchronises `stream`.  Errors: NDQ_ENOCONV (tol not reached; the
  *   best modes found are still written), NDQ_ENOMEM, NDQ_EPREC, NDQ_ENAN. */
 int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double lam_max,
@@ -286,6 +295,18 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
  * interleaved complex `a`, destroyed); w ascending, z columns = eigenvectors
  * (row-major, interleaved complex).  The library's own small-matrix solver. */
 int ndq_host_eigh(int n, double* a, double* w, double* z);
+
+/* ---- derivatives (not in the paper; follow from Eq. 1) --------------------- */
+/* For y = Q[U] psi and a cotangent g (dL = Re<g, dy>): the su(3) link force
+ *   F^a_mu(x) = dL/dw for U_mu(x) -> exp(i w T_a) U_mu(x),  T_a = lambda_a / 2,
+ * into d_force (device, double [V][4][8], lexicographic sites) and/or the
+ * tangent-space gradient 2 i sum_a F^a T_a U_mu(x) into d_grad (device, complex128
+ * [V][4][3][3]), i.e. the gradient with respect to the complex link tensor in the
+ * convention dL = Re<grad, dU>.  (The spinor gradient is Q g: Q is Hermitian.)
+ * FP64 links and spinors, NDQ_FULL, nrhs 1; either output may be NULL, not both.
+ * Asynchronous. */
+int ndq_gauge_force(const ndq_geom* g, const ndq_gauge* U, const ndq_spinor* psi, const ndq_spinor* gy,
+                    double* d_force, void* d_grad, void* stream);
 
 /* ---- launch tuning ------------------------------------------------------ */
 /* Launch shape of the stencil kernels: `block` = 64, 128 or 256 lanes with one

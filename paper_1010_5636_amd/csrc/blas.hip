@@ -407,6 +407,34 @@ __global__ void __launch_bounds__(kBlock) k_rotate(const char* __restrict__ src,
     }
 }
 
+// out = start * exp(i theta) per component, theta = 2 pi u with u from the
+// splitmix64 hash of (index, site, component): a deterministic family of
+// independent start vectors derived from one (index 0 returns start itself).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(kBlock) k_phase_copy(SpinorView src, SpinorView dst, int idx, int32_t n) {
+    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    C<double> x[12];
+    SpinorIO<P64>::load(src, s, x);
+    if (idx > 0) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const uint64_t h = splitmix64(((uint64_t)idx << 40) ^ ((uint64_t)s * 12u + (uint64_t)c));
+            const double u = (double)(h >> 11) * 0x1.0p-53;
+            double sn, cs;
+            sincos(6.283185307179586 * u, &sn, &cs);
+            x[c] = cmul(x[c], C<double>{cs, sn});
+        }
+    }
+    SpinorIO<P64>::store(dst, s, x);
+}
+
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -524,6 +552,13 @@ int mode_update(const ndq_geom* g, const void* modes, int nev, const double* coe
 int mode_coef(const double* c, const double* d, const ModeSigns& sg, int use_sign, int nev, double sc, double sd,
               double* coef, hipStream_t st) {
     hipLaunchKernelGGL(k_mode_coef, dim3(1), dim3(NDQ_MAX_MODES), 0, st, c, d, sg, use_sign, nev, sc, sd, coef);
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int phase_copy(const ndq_geom* g, const ndq_spinor* src, const ndq_spinor* dst, int idx, hipStream_t st) {
+    hipLaunchKernelGGL(k_phase_copy, dim3(nblocks(g->volume)), dim3(kBlock), 0, st, flat_view(g, src),
+                       flat_view(g, dst), idx, (int32_t)g->volume);
     NDQ_HIP(hipGetLastError());
     return NDQ_OK;
 }

@@ -3,7 +3,13 @@
 // residues rho_k = |(Q - nu_k) u_k| (Eq. 8), kappa_+- (Eq. 9) and the projector
 // bound of Eq. 10.
 //
-// V is found by thick-restart Lanczos (Wu & Simon) on B = T_d(A~), a Chebyshev
+// Two methods find V, both built on the Chebyshev filter B = T_d(A~):
+//  * block Chebyshev-filtered subspace iteration (default; Zhou & Saad): a block
+//    of nev + nextra vectors is filtered, orthonormalised and rotated onto the
+//    Ritz vectors of Q each iteration; the cutoff a follows the block's largest
+//    Ritz value of Q^2 and the degree d the gap to the guard pair, so the filter
+//    sharpens as the block converges; degenerate eigenspaces are no obstacle;
+//  * thick-restart Lanczos (Wu & Simon) on B = T_d(A~), a Chebyshev
 // polynomial of A = Q^2 mapped from [a, lam_max^2] onto [-1, 1]: the low end of
 // the spectrum (below the cutoff a) becomes the dominant part of B's spectrum.
 // Every Lanczos vector is orthogonalised twice against the whole basis
@@ -141,6 +147,148 @@ void eig_T(const std::vector<cd>& T, int m, std::vector<double>& w, std::vector<
     hermitian_eig(m, a, w, z);
 }
 
+// Rayleigh-Ritz of Q in span(X[0..nb-1]) (orthonormal): W = Q X, M = X^H W.
+// The Ritz pairs (nu_j, u_j) are ordered by theta_j = |Q u_j|^2 = z_j^H (W^H W) z_j,
+// the Rayleigh quotient of A = Q^2, not by |nu_j|: Q is indefinite, and a
+// block vector still mixing eigenvectors of opposite sign has a Ritz value
+// near zero while theta stays large, so ordering by theta keeps such spurious
+// pairs out of the wanted set.  X and W are rotated in place onto the ordered
+// Ritz vectors (via the scratch blocks XS, WS) when `rotate_block`, and the
+// first nsel pairs are written to UU / QU with their residues |Q u - nu u|.
+// For the guard pair (index nsel - 1) also the residue of A,
+// r = |A u - theta u|, so that an eigenvalue of A lies in [theta - r, theta + r].
+struct RRResult {
+    std::vector<double> nu;      // all nb Ritz values of Q, in theta order
+    std::vector<double> theta;   // all nb Rayleigh quotients of A
+    std::vector<double> rho;     // residues of Q for the first nsel
+    double guard_res = 0.0;      // |A u - theta u| of pair nsel - 1
+};
+
+int rayleigh_ritz_q(LmCtx& c, char*& X, char*& W, char*& XS, char*& WS, int nb, int nsel, bool rotate_block,
+                    RRResult& out) {
+    const ndq_geom* g = c.g;
+    int rc;
+    for (int i = 0; i < nb; ++i) {
+        const ndq_spinor xi = c.vec(X, i), wi = c.vec(W, i);
+        if ((rc = c.qapply(&xi, &wi, 1.0))) return rc;
+    }
+    std::vector<cd> M((size_t)nb * nb), G((size_t)nb * nb), col;
+    for (int i = 0; i < nb; ++i) {
+        const ndq_spinor wi = c.vec(W, i);
+        if ((rc = c.dots_to_host(X, nb, &wi, col))) return rc;
+        for (int k = 0; k < nb; ++k) M[(size_t)k * nb + i] = col[k];
+        if ((rc = c.dots_to_host(W, nb, &wi, col))) return rc;
+        for (int k = 0; k < nb; ++k) G[(size_t)k * nb + i] = col[k];
+    }
+    for (int i = 0; i < nb; ++i) {
+        M[(size_t)i * nb + i] = M[(size_t)i * nb + i].real();
+        for (int k = i + 1; k < nb; ++k) {
+            const cd avg = 0.5 * (M[(size_t)i * nb + k] + std::conj(M[(size_t)k * nb + i]));
+            M[(size_t)i * nb + k] = avg;
+            M[(size_t)k * nb + i] = std::conj(avg);
+        }
+    }
+    std::vector<double> nuv;
+    std::vector<cd> zq;
+    hermitian_eig(nb, M, nuv, zq);
+    std::vector<double> th(nb);
+    for (int j = 0; j < nb; ++j) {
+        double t = 0.0;
+        for (int i = 0; i < nb; ++i) {
+            cd gz = 0.0;
+            for (int k = 0; k < nb; ++k) gz += G[(size_t)i * nb + k] * zq[(size_t)k * nb + j];
+            t += (std::conj(zq[(size_t)i * nb + j]) * gz).real();
+        }
+        th[j] = t;
+    }
+    std::vector<int> idx(nb);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int i, int j) { return th[i] < th[j]; });
+    const int ncol = rotate_block ? nb : nsel;
+    std::vector<cd> Z((size_t)nb * ncol);
+    out.nu.resize(nb);
+    out.theta.resize(nb);
+    for (int j = 0; j < nb; ++j) {
+        out.nu[j] = nuv[idx[j]];
+        out.theta[j] = th[idx[j]];
+    }
+    for (int j = 0; j < ncol; ++j)
+        for (int i = 0; i < nb; ++i) Z[(size_t)i * ncol + j] = zq[(size_t)i * nb + idx[j]];
+    NDQ_HIP(hipMemcpyAsync(c.Ydev, Z.data(), sizeof(cd) * Z.size(), hipMemcpyHostToDevice, c.st));
+    char* Xr = c.UU;
+    char* Wr = c.QU;
+    if (rotate_block) {
+        if ((rc = rotate(g, X, nb, c.Ydev, nb, XS, c.st))) return rc;
+        if ((rc = rotate(g, W, nb, c.Ydev, nb, WS, c.st))) return rc;
+        std::swap(X, XS);
+        std::swap(W, WS);
+        Xr = X;
+        Wr = W;
+    } else {
+        if ((rc = rotate(g, X, nb, c.Ydev, nsel, c.UU, c.st))) return rc;
+        if ((rc = rotate(g, W, nb, c.Ydev, nsel, c.QU, c.st))) return rc;
+    }
+    out.rho.assign(nsel, 0.0);
+    for (int k = 0; k < nsel; ++k) {
+        const ndq_spinor qu = c.vec(Wr, k);
+        const ndq_spinor uk = c.vec(Xr, k);
+        const ndq_spinor* v[2] = {&qu, &uk};
+        const Coef cf[2] = {Coef{1.0, nullptr}, Coef{-out.nu[k], nullptr}};
+        if ((rc = lincomb(g, NDQ_F64, &c.X0, 2, v, cf, nullptr, nullptr, c.st))) return rc;
+        double r2;
+        if ((rc = c.norm2(&c.X0, &r2))) return rc;
+        out.rho[k] = sqrt(r2);
+    }
+    {
+        const ndq_spinor qu = c.vec(Wr, nsel - 1);
+        const ndq_spinor uk = c.vec(Xr, nsel - 1);
+        if ((rc = c.qapply(&qu, &c.X1, 1.0))) return rc;
+        const ndq_spinor* v[2] = {&c.X1, &uk};
+        const Coef cf[2] = {Coef{1.0, nullptr}, Coef{-out.theta[nsel - 1], nullptr}};
+        if ((rc = lincomb(g, NDQ_F64, &c.X0, 2, v, cf, nullptr, nullptr, c.st))) return rc;
+        double r2;
+        if ((rc = c.norm2(&c.X0, &r2))) return rc;
+        out.guard_res = sqrt(r2);
+    }
+    if (rotate_block && Xr != c.UU) {
+        NDQ_HIP(hipMemcpyAsync(c.UU, Xr, (size_t)c.vb * nsel, hipMemcpyDeviceToDevice, c.st));
+    }
+    return NDQ_OK;
+}
+
+// Orthonormalise the block X[0..nb-1] in place (classical Gram-Schmidt, twice).
+int orthonormalise(LmCtx& c, char* X, int nb) {
+    int rc;
+    std::vector<cd> h;
+    for (int j = 0; j < nb; ++j) {
+        const ndq_spinor xj = c.vec(X, j);
+        for (int pass = 0; pass < 2 && j > 0; ++pass) {
+            if ((rc = c.dots_to_host(X, j, &xj, h))) return rc;
+            if ((rc = c.subtract(X, j, h, &xj))) return rc;
+        }
+        double n2;
+        if ((rc = c.norm2(&xj, &n2))) return rc;
+        if (!(n2 > 0) || !isfinite(n2)) return fail(NDQ_ENAN, "low modes: block lost rank or overflowed");
+        if ((rc = c.copy(&xj, &xj, 1.0 / sqrt(n2)))) return rc;
+    }
+    return NDQ_OK;
+}
+
+// Degree of the filter T_d on [a, b]: large enough to gain a factor ~2e3 at the
+// guard eigenvalue per application, but with T_d(x(0)) <= 1e10 (A = Q^2 >= 0, so
+// no eigenvalue is amplified more): a larger contrast than ~1/eps would leave the
+// weakly amplified block vectors as rounding noise after orthogonalisation.
+int filter_degree(double a, double b, double lam_guard) {
+    const double x = 1.0 + 2.0 * (a - lam_guard) / (b - a);
+    const double grow = x > 1.0 ? acosh(x) : 0.0;
+    int d = grow > 0 ? (int)ceil(log(2e3) / grow) : 400;
+    const double x0 = 1.0 + 2.0 * a / (b - a);
+    const int dmax = (int)floor(log(2e10) / acosh(x0));
+    d = std::min(d, dmax);
+    d = std::min(400, std::max(4, d));
+    return d + (d & 1);
+}
+
 }  // namespace
 }  // namespace ndq
 
@@ -149,15 +297,18 @@ using namespace ndq;
 extern "C" {
 
 size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params* p) {
-    if (!g || !p || p->nev < 1 || p->basis < 2) return 0;
+    if (!g || !p || p->nev < 1) return 0;
     const size_t vb = (size_t)spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
-    const int m = p->basis, nkeep = p->nev + std::max(p->nextra, 1);
+    const int nkeep = p->nev + std::max(p->nextra, 1);
+    const int m = p->method == NDQ_LM_LANCZOS ? p->basis : nkeep;
+    if (m < 2) return 0;
     Arena ar{nullptr, 0};
-    ar.take(vb * (m + 1));
-    ar.take(vb * (m + 1));
-    ar.take(vb * nkeep);
-    ar.take(vb * (p->nev + 1));
-    ar.take(vb * (p->nev + 1));
+    ar.take(vb * (m + 1));          // VA
+    ar.take(vb * (m + 1));          // VB
+    ar.take(vb * nkeep);            // W
+    ar.take(vb * nkeep);            // WS
+    ar.take(vb * (p->nev + 1));     // QU
+    ar.take(vb * (p->nev + 1));     // UU
     for (int i = 0; i < 3; ++i) ar.take(vb);
     ar.take(partials_capacity(g, 2 * NDQ_MAX_MODES));
     ar.take(2 * NDQ_MAX_MODES * sizeof(double));
@@ -176,9 +327,13 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     if (!rc) rc = check_spinor(g, start, NDQ_FULL, "ndq_lowmodes_compute start");
     if (rc) return rc;
     if (U->prec != NDQ_F64 || start->prec != NDQ_F64) return fail(NDQ_EPREC, "low modes: FP64 links and start vector");
-    const int nev = p->nev, nkeep = nev + std::max(p->nextra, 1), mb = p->basis;
-    if (nev < 1 || mb > NDQ_MAX_MODES - 1 || mb < nkeep + 2)
-        return fail(NDQ_EINVAL, "low modes: need 1 <= nev, nev + nextra + 2 <= basis <= %d", NDQ_MAX_MODES - 1);
+    const bool lanczos = p->method == NDQ_LM_LANCZOS;
+    if (p->method != NDQ_LM_SUBSPACE && !lanczos) return fail(NDQ_EINVAL, "low modes: unknown method %d", p->method);
+    const int nev = p->nev, nkeep = nev + std::max(p->nextra, 1);
+    const int mb = lanczos ? p->basis : nkeep;
+    if (nev < 1 || nkeep > NDQ_MAX_MODES || (lanczos && (mb > NDQ_MAX_MODES - 1 || mb < nkeep + 2)))
+        return fail(NDQ_EINVAL, "low modes: need 1 <= nev, nev + nextra <= %d (Lanczos: nev + nextra + 2 <= basis <= %d)",
+                    NDQ_MAX_MODES, NDQ_MAX_MODES - 1);
     if (!(lam_max > 0)) return fail(NDQ_EINVAL, "low modes: lam_max must be positive");
     LmCtx c;
     c.g = g;
@@ -190,6 +345,7 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     c.VA = static_cast<char*>(ar.take(c.vb * (mb + 1)));
     c.VB = static_cast<char*>(ar.take(c.vb * (mb + 1)));
     c.W = static_cast<char*>(ar.take(c.vb * nkeep));
+    char* WS = static_cast<char*>(ar.take(c.vb * nkeep));
     c.QU = static_cast<char*>(ar.take(c.vb * (nev + 1)));
     c.UU = static_cast<char*>(ar.take(c.vb * (nev + 1)));
     c.X0 = ws_spinor(ar, g, NDQ_F64);
@@ -202,153 +358,147 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     c.scal = static_cast<double*>(ar.take(64 * sizeof(double)));
     if (ar.overflow) return fail(NDQ_ENOMEM, "low modes: workspace too small (need %zu bytes)", ar.used);
     const double b = lam_max * lam_max;
+    const double tol = p->tol > 0 ? p->tol : 1e-10;
+    const double guard_tol = std::max(tol, 1e-6);
+    const int max_restarts = p->max_restarts > 0 ? p->max_restarts : (lanczos ? 100 : 200);
+    const int nsel = nev + 1;
 
-    // v0 = start / |start|
     double s2;
-    {
-        const ndq_spinor v0 = c.vec(c.VA, 0);
-        if ((rc = c.norm2(start, &s2))) return rc;
-        if (!(s2 > 0) || !isfinite(s2)) return fail(NDQ_EINVAL, "low modes: zero or non-finite start vector");
-        if ((rc = c.copy(&v0, start, 1.0 / sqrt(s2)))) return rc;
-    }
+    if ((rc = c.norm2(start, &s2))) return rc;
+    if (!(s2 > 0) || !isfinite(s2)) return fail(NDQ_EINVAL, "low modes: zero or non-finite start vector");
 
-    // cutoff a and degree d from a plain Lanczos run on A = Q^2
     double a = p->cheb_lo;
     int d = p->cheb_degree;
-    if (!(a > 0) || d <= 0) {
-        const int m0 = mb;
-        std::vector<cd> T((size_t)m0 * m0, 0.0);
-        if ((rc = lanczos_steps(c, c.VA, 0, m0, T, 0, 0, 0, 0))) return rc;
-        std::vector<double> th;
-        std::vector<cd> z;
-        eig_T(T, m0, th, z);
-        if (!(a > 0)) a = th[std::min(nkeep, m0 - 1)];
-        if (d <= 0) {
-            const double lw = th[nev - 1];
-            const double x = 1.0 + 2.0 * (a - lw) / (b - a);
-            const double grow = x > 1.0 ? acosh(x) : 0.0;
-            d = grow > 0 ? (int)ceil(log(1e4) / grow) : 600;
-            d = std::min(600, std::max(16, d + (d & 1)));
-        }
-        // restart the filtered run from the original start vector
-        const ndq_spinor v0 = c.vec(c.VA, 0);
-        if ((rc = c.copy(&v0, start, 1.0 / sqrt(s2)))) return rc;
-    }
-    if (!(a > 0 && a < b)) return fail(NDQ_EINVAL, "low modes: filter cutoff %g outside (0, lam_max^2)", a);
-
-    std::vector<cd> T((size_t)mb * mb, 0.0);
-    int j0 = 0;
     int restarts = 0;
-    const int max_restarts = p->max_restarts > 0 ? p->max_restarts : 50;
-    const double tol = p->tol > 0 ? p->tol : 1e-10;
-    std::vector<double> nu_sel(nev), rho_sel(nev);
-    double lam_next = 0.0, max_rho = 0.0, rho_next = 0.0;
-    const double guard_tol = std::max(tol, 1e-6);
     bool converged = false;
-    for (;;) {
-        if ((rc = lanczos_steps(c, c.VA, j0, mb, T, 1, a, b, d))) return rc;
-        std::vector<double> th;
-        std::vector<cd> z;
-        eig_T(T, mb, th, z);
-        // keep the nkeep largest B-Ritz pairs (descending)
-        std::vector<cd> Y((size_t)mb * nkeep);
-        std::vector<double> thk(nkeep);
-        for (int j = 0; j < nkeep; ++j) {
-            const int col = mb - 1 - j;
-            thk[j] = th[col];
-            for (int i = 0; i < mb; ++i) Y[(size_t)i * nkeep + j] = z[(size_t)i * mb + col];
-        }
-        NDQ_HIP(hipMemcpyAsync(c.Ydev, Y.data(), sizeof(cd) * Y.size(), hipMemcpyHostToDevice, c.st));
-        if ((rc = rotate(g, c.VA, mb, c.Ydev, nkeep, c.VB, c.st))) return rc;
-        {
-            const ndq_spinor r = c.vec(c.VA, mb), dst = c.vec(c.VB, nkeep);
-            if ((rc = c.copy(&dst, &r))) return rc;
-        }
-        std::swap(c.VA, c.VB);
-        ++restarts;
+    RRResult rr;
+    char* X = c.VA;
+    char* XS = c.VB;
+    char* W = c.W;
 
-        // Rayleigh-Ritz of Q in span(VA[0..nkeep-1])
+    if (!lanczos) {
+        // ---- Chebyshev-filtered subspace iteration on a block of nkeep vectors
         for (int i = 0; i < nkeep; ++i) {
-            const ndq_spinor vi = c.vec(c.VA, i), wi = c.vec(c.W, i);
-            if ((rc = c.qapply(&vi, &wi, 1.0))) return rc;
+            const ndq_spinor xi = c.vec(X, i);
+            if ((rc = phase_copy(g, start, &xi, i, c.st))) return rc;
         }
-        std::vector<cd> M((size_t)nkeep * nkeep), col;
-        for (int i = 0; i < nkeep; ++i) {
-            const ndq_spinor wi = c.vec(c.W, i);
-            if ((rc = c.dots_to_host(c.VA, nkeep, &wi, col))) return rc;
-            for (int k = 0; k < nkeep; ++k) M[(size_t)k * nkeep + i] = col[k];
-        }
-        for (int i = 0; i < nkeep; ++i)
-            for (int k = i + 1; k < nkeep; ++k) {
-                const cd avg = 0.5 * (M[(size_t)i * nkeep + k] + std::conj(M[(size_t)k * nkeep + i]));
-                M[(size_t)i * nkeep + k] = avg;
-                M[(size_t)k * nkeep + i] = std::conj(avg);
+        if ((rc = orthonormalise(c, X, nkeep))) return rc;
+        // initial cutoff: the largest Rayleigh quotient |Q x|^2 of the start block
+        if (!(a > 0)) {
+            a = 0.0;
+            for (int i = 0; i < nkeep; ++i) {
+                const ndq_spinor xi = c.vec(X, i), wi = c.vec(W, i);
+                if ((rc = c.qapply(&xi, &wi, 1.0))) return rc;
+                double q2;
+                if ((rc = c.norm2(&wi, &q2))) return rc;
+                a = std::max(a, q2);
             }
-        std::vector<double> nuv;
-        std::vector<cd> zq;
-        hermitian_eig(nkeep, M, nuv, zq);
-        std::vector<int> idx(nkeep);
-        std::iota(idx.begin(), idx.end(), 0);
-        std::stable_sort(idx.begin(), idx.end(), [&](int i, int j) { return fabs(nuv[i]) < fabs(nuv[j]); });
-        // the nev modes plus the next one (its eigenvalue is lam_next; it must be
-        // converged too, or an eigenvalue could hide between |nu_nev| and lam_next)
-        const int nsel = nev + 1;
-        std::vector<cd> Zs((size_t)nkeep * nsel);
-        std::vector<double> nu_all(nsel), rho_all(nsel);
-        for (int j = 0; j < nsel; ++j) {
-            nu_all[j] = nuv[idx[j]];
-            for (int i = 0; i < nkeep; ++i) Zs[(size_t)i * nsel + j] = zq[(size_t)i * nkeep + idx[j]];
+            a = std::min(a, 0.5 * b);
         }
-        lam_next = fabs(nu_all[nev]);
-        NDQ_HIP(hipMemcpyAsync(c.Ydev, Zs.data(), sizeof(cd) * Zs.size(), hipMemcpyHostToDevice, c.st));
-        if ((rc = rotate(g, c.VA, nkeep, c.Ydev, nsel, c.UU, c.st))) return rc;
-        if ((rc = rotate(g, c.W, nkeep, c.Ydev, nsel, c.QU, c.st))) return rc;
-        max_rho = 0.0;
-        for (int k = 0; k < nsel; ++k) {
-            const ndq_spinor qu = c.vec(c.QU, k);
-            const ndq_spinor uk = c.vec(c.UU, k);
-            const ndq_spinor* v[2] = {&qu, &uk};
-            const Coef cf[2] = {Coef{1.0, nullptr}, Coef{-nu_all[k], nullptr}};
-            if ((rc = lincomb(g, NDQ_F64, &c.X0, 2, v, cf, nullptr, nullptr, c.st))) return rc;
-            double r2;
-            if ((rc = c.norm2(&c.X0, &r2))) return rc;
-            rho_all[k] = sqrt(r2);
-            if (k < nev) max_rho = std::max(max_rho, rho_all[k]);
+        const bool fixed_d = d > 0;
+        if (!fixed_d) d = filter_degree(a, b, 0.5 * a);
+        for (;;) {
+            for (int i = 0; i < nkeep; ++i) {
+                const ndq_spinor xi = c.vec(X, i), yi = c.vec(XS, i);
+                if ((rc = apply_filter(c, &xi, &yi, a, b, d))) return rc;
+            }
+            std::swap(X, XS);
+            if ((rc = orthonormalise(c, X, nkeep))) return rc;
+            if ((rc = rayleigh_ritz_q(c, X, W, XS, WS, nkeep, nsel, true, rr))) return rc;
+            ++restarts;
+            double max_rho = 0.0;
+            for (int k = 0; k < nev; ++k) max_rho = std::max(max_rho, rr.rho[k]);
+            if (max_rho <= tol * lam_max && rr.guard_res <= guard_tol * b) {
+                converged = true;
+                break;
+            }
+            if (restarts >= max_restarts) break;
+            // sharpen the filter: cutoff at the block's largest Rayleigh quotient of A
+            a = std::min(std::max(rr.theta[nkeep - 1], 1e-12), 0.9 * b);
+            if (!fixed_d) d = filter_degree(a, b, rr.theta[nev]);
         }
-        for (int k = 0; k < nev; ++k) {
-            nu_sel[k] = nu_all[k];
-            rho_sel[k] = rho_all[k];
+    } else {
+        // ---- thick-restart Lanczos on the filter
+        {
+            const ndq_spinor v0 = c.vec(c.VA, 0);
+            if ((rc = c.copy(&v0, start, 1.0 / sqrt(s2)))) return rc;
         }
-        rho_next = rho_all[nev];
-        NDQ_HIP(hipMemcpyAsync(d_modes, c.UU, (size_t)c.vb * nev, hipMemcpyDeviceToDevice, c.st));
-        NDQ_HIP(hipStreamSynchronize(c.st));
-        // the returned modes to tol; the next pair only to guard_tol, enough for
-        // lam_next - rho_next to bound the next eigenvalue's modulus from below
-        if (max_rho <= tol * lam_max && rho_next <= guard_tol * lam_max) {
-            converged = true;
-            break;
+        if (!(a > 0) || d <= 0) {
+            const int m0 = mb;
+            std::vector<cd> T((size_t)m0 * m0, 0.0);
+            if ((rc = lanczos_steps(c, c.VA, 0, m0, T, 0, 0, 0, 0))) return rc;
+            std::vector<double> th;
+            std::vector<cd> z;
+            eig_T(T, m0, th, z);
+            if (!(a > 0)) a = th[std::min(nkeep, m0 - 1)];
+            if (d <= 0) d = filter_degree(a, b, th[nev - 1]);
+            const ndq_spinor v0 = c.vec(c.VA, 0);
+            if ((rc = c.copy(&v0, start, 1.0 / sqrt(s2)))) return rc;
         }
-        if (restarts >= max_restarts) break;
-        // thick restart: T = diag(theta) on the kept block, new column from V[nkeep]
-        std::fill(T.begin(), T.end(), cd(0.0, 0.0));
-        for (int j = 0; j < nkeep; ++j) T[(size_t)j * mb + j] = thk[j];
-        j0 = nkeep;
+        if (!(a > 0 && a < b)) return fail(NDQ_EINVAL, "low modes: filter cutoff %g outside (0, lam_max^2)", a);
+        std::vector<cd> T((size_t)mb * mb, 0.0);
+        int j0 = 0;
+        for (;;) {
+            if ((rc = lanczos_steps(c, c.VA, j0, mb, T, 1, a, b, d))) return rc;
+            std::vector<double> th;
+            std::vector<cd> z;
+            eig_T(T, mb, th, z);
+            std::vector<cd> Y((size_t)mb * nkeep);
+            std::vector<double> thk(nkeep);
+            for (int j = 0; j < nkeep; ++j) {
+                const int col = mb - 1 - j;
+                thk[j] = th[col];
+                for (int i = 0; i < mb; ++i) Y[(size_t)i * nkeep + j] = z[(size_t)i * mb + col];
+            }
+            NDQ_HIP(hipMemcpyAsync(c.Ydev, Y.data(), sizeof(cd) * Y.size(), hipMemcpyHostToDevice, c.st));
+            if ((rc = rotate(g, c.VA, mb, c.Ydev, nkeep, c.VB, c.st))) return rc;
+            {
+                const ndq_spinor r = c.vec(c.VA, mb), dst = c.vec(c.VB, nkeep);
+                if ((rc = c.copy(&dst, &r))) return rc;
+            }
+            std::swap(c.VA, c.VB);
+            ++restarts;
+            char* Xl = c.VA;
+            char* Wl = c.W;
+            char* dummy1 = nullptr;
+            char* dummy2 = nullptr;
+            if ((rc = rayleigh_ritz_q(c, Xl, Wl, dummy1, dummy2, nkeep, nsel, false, rr))) return rc;
+            double max_rho = 0.0;
+            for (int k = 0; k < nev; ++k) max_rho = std::max(max_rho, rr.rho[k]);
+            if (max_rho <= tol * lam_max && rr.guard_res <= guard_tol * b) {
+                converged = true;
+                break;
+            }
+            if (restarts >= max_restarts) break;
+            std::fill(T.begin(), T.end(), cd(0.0, 0.0));
+            for (int j = 0; j < nkeep; ++j) T[(size_t)j * mb + j] = thk[j];
+            j0 = nkeep;
+        }
     }
+    // results: the first nev Ritz pairs (in theta order), guard pair -> lam_next
+    NDQ_HIP(hipMemcpyAsync(d_modes, c.UU, (size_t)c.vb * nev, hipMemcpyDeviceToDevice, c.st));
+    NDQ_HIP(hipStreamSynchronize(c.st));
+    double max_rho = 0.0;
     for (int k = 0; k < nev; ++k) {
-        nu[k] = nu_sel[k];
-        rho[k] = rho_sel[k];
+        nu[k] = rr.nu[k];
+        rho[k] = rr.rho[k];
+        max_rho = std::max(max_rho, rr.rho[k]);
     }
+    // guard: A has an eigenvalue in [theta - r, theta + r] (r = |A u - theta u|),
+    // so |Q| has one at or above sqrt(theta - r) = lam_next - rho_next
+    const double lam_next = sqrt(std::max(rr.theta[nev], 0.0));
+    const double rho_next = lam_next - sqrt(std::max(rr.theta[nev] - rr.guard_res, 0.0));
     if (info) {
         memset(info, 0, sizeof(*info));
         info->lam_next = lam_next;
         // Eq. 9 with d_k = min(lam_next - |nu_k|, |nu_k| + min over opposite-sign |nu_j|)
         double kp2 = 0.0, km2 = 0.0;
         for (int k = 0; k < nev; ++k) {
-            double dk = lam_next - fabs(nu_sel[k]);
+            double dk = lam_next - fabs(nu[k]);
             for (int j = 0; j < nev; ++j)
-                if ((nu_sel[j] > 0) != (nu_sel[k] > 0)) dk = std::min(dk, fabs(nu_sel[k]) + fabs(nu_sel[j]));
-            const double q = dk > 0 ? rho_sel[k] / dk : INFINITY;
-            (nu_sel[k] > 0 ? kp2 : km2) += q * q;
+                if ((nu[j] > 0) != (nu[k] > 0)) dk = std::min(dk, fabs(nu[k]) + fabs(nu[j]));
+            const double q = dk > 0 ? rho[k] / dk : INFINITY;
+            (nu[k] > 0 ? kp2 : km2) += q * q;
         }
         info->kappa_plus = sqrt(kp2);
         info->kappa_minus = sqrt(km2);
@@ -368,8 +518,8 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     if (!converged)
-        return fail(NDQ_ENOCONV, "low modes: max rho %.3e (next %.3e) > %.3e after %d restarts", max_rho, rho_next,
-                    tol * lam_max, restarts);
+        return fail(NDQ_ENOCONV, "low modes: max rho %.3e (guard residue of Q^2 %.3e) > %.3e after %d iterations",
+                    max_rho, rr.guard_res, tol * lam_max, restarts);
     return NDQ_OK;
 }
 

@@ -89,6 +89,10 @@ int mode_update(const ndq_geom* g, const void* modes, int nev, const double* coe
 // Y complex row-major [nsrc][k] in device memory; dst must not overlap src.
 int rotate(const ndq_geom* g, const void* src, int nsrc, const double* Y, int k, void* dst, hipStream_t st);
 
+// dst = src * exp(i theta(idx, site, component)), a hashed unit phase per
+// component (idx = 0: plain copy); FP64 full fields.
+int phase_copy(const ndq_geom* g, const ndq_spinor* src, const ndq_spinor* dst, int idx, hipStream_t st);
+
 // ---- multi-shift CG device state (blas.hip) ---------------------------------
 struct MsState {
     double b2;                        // |b|^2

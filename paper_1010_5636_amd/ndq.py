@@ -22,6 +22,7 @@ F64, F32, F16 = 0, 1, 2
 EVEN, ODD, FULL = 0, 1, 2
 ZOLOTAREV, MINMAX_POLY = 0, 1
 LITERAL, SANDWICH = 0, 1
+LM_SUBSPACE, LM_LANCZOS = 0, 1
 OP_SIGN, OP_DN, OP_SOLVE = 0, 1, 2
 
 STATUS = {0: "NDQ_OK", -1: "NDQ_EINVAL", -2: "NDQ_EDIMS", -3: "NDQ_EPREC", -4: "NDQ_ENOMEM",
@@ -61,7 +62,7 @@ class _Stats(ctypes.Structure):
 class _LmParams(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int32), ("nextra", ctypes.c_int32), ("basis", ctypes.c_int32),
                 ("cheb_degree", ctypes.c_int32), ("cheb_lo", ctypes.c_double), ("tol", ctypes.c_double),
-                ("max_restarts", ctypes.c_int32)]
+                ("max_restarts", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class _LmInfo(ctypes.Structure):
@@ -120,6 +121,8 @@ _SIG = {
     "ndq_solve_DN": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Gauge), ctypes.POINTER(_Params),
                           ctypes.POINTER(_Params), ctypes.POINTER(_SolveParams), ctypes.POINTER(_Spinor),
                           ctypes.POINTER(_Spinor), _P, ctypes.c_size_t, ctypes.POINTER(_Stats), _P]),
+    "ndq_gauge_force": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P, _P,
+                             _P]),
     "ndq_set_launch": (_I, [_I, _I]),
     "ndq_set_launch_for": (_I, [_I, _I, _I, _I, _I]),
 }
@@ -378,11 +381,11 @@ def apply_DN(geom: Geometry, U: GaugeField, ov: Overlap, inp: SpinorField, out: 
 
 def lowmodes_compute(geom: Geometry, U: GaugeField, m: float, lam_max: float, start: SpinorField, nev: int,
                      nextra: int = 8, basis: int = 0, cheb_degree: int = 0, cheb_lo: float = 0.0, tol: float = 1e-10,
-                     max_restarts: int = 50, stream=None):
+                     max_restarts: int = 0, method: int = 0, stream=None):
     """Low modes of Q: returns (modes SpinorField (F64, FULL, nrhs=nev), nu, rho, info dict)."""
     import numpy as np
     basis = basis or min(63, nev + nextra + max(12, nev))
-    p = _LmParams(nev, nextra, basis, cheb_degree, cheb_lo, tol, max_restarts)
+    p = _LmParams(nev, nextra, basis, cheb_degree, cheb_lo, tol, max_restarts, method)
     nbytes = int(lib().ndq_lowmodes_workspace_bytes(geom.handle, ctypes.byref(p)))
     if nbytes == 0:
         raise NdqError(-1, "bad low-mode parameters")
@@ -426,3 +429,43 @@ def solve_DN(geom: Geometry, U64: GaugeField, ov64: Overlap, b: SpinorField, x: 
                               ctypes.byref(ov64.p), plo, ctypes.byref(sp), ctypes.byref(b.desc), ctypes.byref(x.desc),
                               _ptr(ws), n, ctypes.byref(st), _stream(stream)))
     return st.as_dict()
+
+
+def gauge_force(geom: Geometry, U: GaugeField, psi: SpinorField, g: SpinorField, want_force: bool = True,
+                want_grad: bool = False, stream=None):
+    """(force [V,4,8] float64 or None, tangent gradient [V,4,3,3] complex128 or None) for
+    y = Q[U] psi and cotangent g."""
+    v = geom.volume
+    f = torch.empty((v, 4, 8), dtype=torch.float64, device="cuda") if want_force else None
+    gr = torch.empty((v, 4, 3, 3), dtype=torch.complex128, device="cuda") if want_grad else None
+    _check(lib().ndq_gauge_force(geom.handle, ctypes.byref(U.desc), ctypes.byref(psi.desc), ctypes.byref(g.desc),
+                                 None if f is None else _ptr(f), None if gr is None else _ptr(gr), _stream(stream)))
+    return f, gr
+
+
+class QFunction(torch.autograd.Function):
+    """y = Q[U] psi on canonical complex128 GPU tensors (psi [V,4,3], links [V,4,3,3]),
+    differentiable in psi (grad = Q g) and in the links (the su(3) tangent-space
+    gradient from ndq_gauge_force).  Usage: QFunction.apply(psi, links, geom, m)."""
+
+    @staticmethod
+    def forward(ctx, psi, links, geom, m):
+        U = GaugeField.pack(geom, links.detach(), F64, 18)
+        x = SpinorField.pack(geom, psi.detach(), F64, FULL)
+        y = x.like()
+        apply_Q(geom, U, m, x, y)
+        ctx.geom, ctx.m, ctx.U, ctx.x = geom, m, U, x
+        return y.unpack()[0]
+
+    @staticmethod
+    def backward(ctx, gy):
+        geom = ctx.geom
+        gsp = SpinorField.pack(geom, gy.contiguous(), F64, FULL)
+        gpsi = glinks = None
+        if ctx.needs_input_grad[0]:
+            out = gsp.like()
+            apply_Q(geom, ctx.U, ctx.m, gsp, out)
+            gpsi = out.unpack()[0]
+        if ctx.needs_input_grad[1]:
+            _, glinks = gauge_force(geom, ctx.U, ctx.x, gsp, want_force=False, want_grad=True)
+        return gpsi, glinks, None, None

@@ -5,6 +5,9 @@
   true projector deviation, and sign(Q) with these modes vs the oracle's closed
   form with exact modes.
 * 8^4 random links, l = 12: residues recomputed by the oracle's stencil.
+* 4^4 free field, l = 48 (block method): the exactly 48-fold degenerate
+  |lambda| = 0.6 eigenspace, projector against the exact one.
+Both methods (block subspace iteration, thick-restart Lanczos) are exercised.
 """
 import numpy as np
 import pytest
@@ -28,13 +31,17 @@ def cu(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
 
 
-def run(dims, u, nev, nextra=8, tol=1e-11, basis=0):
+def run(dims, u, nev, nextra=8, tol=1e-11, basis=0, method=ndq.ndq.LM_SUBSPACE):
     g = ndq.Geometry(dims)
     U = ndq.GaugeField.pack(g, cu(u), ndq.F64, 18)
     v = geometry.volume(dims)
     start = ndq.SpinorField.pack(g, cu(synthetic.start_vector(v)), ndq.F64, ndq.FULL)
-    modes, nu, rho, info = ndq.lowmodes_compute(g, U, M, LMAX, start, nev, nextra=nextra, tol=tol, basis=basis)
+    modes, nu, rho, info = ndq.lowmodes_compute(g, U, M, LMAX, start, nev, nextra=nextra, tol=tol, basis=basis,
+                                                method=method)
     return g, U, modes, nu, rho, info
+
+
+METHODS = [ndq.ndq.LM_SUBSPACE, ndq.ndq.LM_LANCZOS]
 
 
 @pytest.fixture(scope="module")
@@ -45,9 +52,10 @@ def dense4():
     return {"u": u, "q": q, "eig": (lam, w), "order": np.argsort(np.abs(lam), kind="stable")}
 
 
-def test_lowmodes_random_4c4(dense4):
+@pytest.mark.parametrize("method", METHODS)
+def test_lowmodes_random_4c4(dense4, method):
     nev = 8
-    g, U, modes, nu, rho, info = run((4, 4, 4, 4), dense4["u"], nev)
+    g, U, modes, nu, rho, info = run((4, 4, 4, 4), dense4["u"], nev, method=method)
     lam = dense4["eig"][0][dense4["order"]]
     assert np.allclose(np.sort(nu), np.sort(lam[:nev]), atol=1e-10), (nu, lam[:nev + 2])
     assert np.all(rho <= 1e-11 * LMAX)
@@ -82,11 +90,12 @@ def test_sign_with_computed_modes(dense4):
     assert np.linalg.norm(got - ref) <= 1e-8 * np.linalg.norm(psi)
 
 
-def test_lowmodes_8c4_residuals():
+@pytest.mark.parametrize("method", METHODS)
+def test_lowmodes_8c4_residuals(method):
     dims = (8, 8, 8, 8)
     u = synthetic.gauge_field(dims, seed=5)
     nev = 12
-    g, U, modes, nu, rho, info = run(dims, u, nev, tol=1e-10)
+    g, U, modes, nu, rho, info = run(dims, u, nev, tol=1e-10, method=method)
     v = geometry.volume(dims)
     um = modes.unpack().cpu().numpy()
     qu = dirac.apply_Q(u, um, M, dims).reshape(nev, -1)
@@ -96,3 +105,21 @@ def test_lowmodes_8c4_residuals():
     assert np.abs(gram - np.eye(nev)).max() < 1e-12
     assert np.all(np.abs(nu) <= info["lam_next"] + 1e-12)
     assert np.all(np.diff(np.abs(nu)) >= -1e-14)
+
+
+def test_lowmodes_free_field_degenerate():
+    """Block subspace iteration resolves the free field's 48-fold |lambda| = 0.6
+    eigenspace (gap to sqrt(1.16)); the projector must equal the exact one."""
+    dims = (4, 4, 4, 4)
+    u = synthetic.cold_gauge(dims)
+    nev = 48
+    g, U, modes, nu, rho, info = run(dims, u, nev, nextra=12)
+    assert np.allclose(np.abs(nu), 0.6, atol=1e-10)
+    assert np.sum(nu > 0) == 24
+    assert abs(info["lam_next"] - np.sqrt(1.16)) < 1e-6
+    um = modes.unpack().cpu().numpy().reshape(nev, -1)
+    q = dirac.dense_Q(u, M, dims)
+    lam, w = np.linalg.eigh(q)
+    pe = w[:, np.abs(np.abs(lam) - 0.6) < 1e-9]
+    assert pe.shape[1] == 48
+    assert np.linalg.norm(um.T @ um.conj() - pe @ pe.conj().T, 2) < 1e-9
