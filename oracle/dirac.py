@@ -96,6 +96,33 @@ def apply_Q(U: np.ndarray, psi: np.ndarray, m: float, dims) -> np.ndarray:
     return gamma5(wilson_dirac(U, psi, m, dims))
 
 
+def apply_Q_at(U: np.ndarray, psi_at, m: float, dims, sites) -> np.ndarray:
+    """(Q psi)(y) for the lexicographic sites y in ``sites`` only (Eq. 1 at those sites).
+
+    ``psi_at(idx)`` returns psi at the lexicographic sites ``idx`` as
+    [..., len(idx), 4, 3]; so psi never has to exist as a full array (large
+    lattices, point sources).  ``U`` is the gauge field [V, 4, 3, 3] or any
+    object indexable as U[site, mu].  The neighbours are found from the
+    coordinates of each site with periodic wrap-around, independently of
+    ``neighbour_table``.
+    """
+    dims = geometry.check_dims(dims)
+    n = np.array(dims)
+    sites = np.asarray(sites, dtype=np.int64)
+    x = np.stack(np.unravel_index(sites, dims), axis=-1)
+    out = (4.0 + m) * psi_at(sites)
+    for mu in range(4):
+        e = np.zeros(4, dtype=np.int64)
+        e[mu] = 1
+        fwd = geometry.lex_of(dims, (x + e) % n)
+        bwd = geometry.lex_of(dims, (x - e) % n)
+        u_f = np.asarray(U[sites, mu])
+        u_b = np.linalg.inv(np.asarray(U[bwd, mu]))
+        out = out - 0.5 * _colour(u_f, _spin(_I4 - _G[mu], psi_at(fwd)))
+        out = out - 0.5 * _colour(u_b, _spin(_I4 + _G[mu], psi_at(bwd)))
+    return gamma5(out)
+
+
 def dslash(U: np.ndarray, psi_in: np.ndarray, dims, out_parity: int) -> np.ndarray:
     """Even/odd hopping block: (H psi)_p for psi living on parity 1-p.
 

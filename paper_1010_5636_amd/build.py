@@ -27,6 +27,9 @@ CFLAGS = [
     "-I", INCLUDE, "-I", CSRC,
     # packed FP32 instructions stay off (they are generated from ordinary float code)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused where the source writes them, not where the
+    # backend finds them: kernels sharing device functions then round alike
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
 ]
 

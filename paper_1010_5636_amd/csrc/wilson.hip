@@ -318,6 +318,115 @@ __global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
     }
 }
 
+// Many right-hand sides on one gauge field: a workgroup of 4 wavefronts owns
+// 64 output sites; it first stages the 8 links of each site into LDS (forward
+// links at the tile's own sites, backward links at the neighbours, 32-bit words
+// with the site index fastest), then wavefront q computes right-hand sides
+// q, q+4, q+8, ... for the 64 sites, decoding links from LDS.  Links leave HBM
+// once per apply instead of once per right-hand side; every spinor load of a
+// wavefront is one right-hand side's 64 consecutive sites.  The per-site
+// arithmetic is that of k_wilson (same hop order and epilogue), so results
+// match the one-lane-per-site kernel bit for bit.
+template <int SP, int LP, int RECON>
+__global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, int nrhs) {
+    using R = typename SpinorIO<SP>::R;
+    using F = LinkFmt<LP, RECON>;
+    extern __shared__ uint32_t lw[];   // [8 dirs][F::kWords][64 sites]
+    unsigned lin = blockIdx.y * gridDim.x + blockIdx.x;
+    if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x * gridDim.y);
+    const int y = (int)(lin / gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int32_t i = (int32_t)(lin - (unsigned)y * gridDim.x) * 64 + lane;
+    const int p = a.p0 + y;
+    const bool active = i < a.g.vh;
+    int32_t nb[8];
+    if (active) {
+        const SiteCoord x = eo_coords(a.g, p, i);
+        eo_neighbours(a.g, i, x, nb);
+        // wavefront w stages the forward link mu = w and the backward link mu = w
+        uint32_t words[F::kWords];
+        link_load_words<LP, RECON>(a.links, a.g.vh, p * 4 + w, i, words);
+#pragma unroll
+        for (int k = 0; k < F::kWords; ++k) lw[(w * F::kWords + k) * 64 + lane] = words[k];
+        link_load_words<LP, RECON>(a.links, a.g.vh, (1 - p) * 4 + w, nb[4 + w], words);
+#pragma unroll
+        for (int k = 0; k < F::kWords; ++k) lw[((4 + w) * F::kWords + k) * 64 + lane] = words[k];
+    }
+    __syncthreads();
+    if (!active) return;
+#pragma unroll 1
+    for (int r = w; r < nrhs; r += 4) {
+        // re-read links from LDS for every right-hand side instead of letting
+        // them be hoisted into registers (which would cost occupancy)
+        int lo = lane;
+        asm volatile("" : "+v"(lo));
+        SpinorView vin = a.in[y];
+        vin.base += (int64_t)r * vin.rhs_bytes;
+        C<R> acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            C<R> sp[12];
+            C<typename LinkReal<LP>::R> u[3][3];
+            uint32_t words[F::kWords];
+            SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[mu], sp);
+#pragma unroll
+            for (int k = 0; k < F::kWords; ++k) words[k] = lw[(mu * F::kWords + k) * 64 + lo];
+            link_decode<LP, RECON>(words, u);
+            if (mu == 0) hop_fwd<0>(sp, u, acc);
+            if (mu == 1) hop_fwd<1>(sp, u, acc);
+            if (mu == 2) hop_fwd<2>(sp, u, acc);
+            if (mu == 3) hop_fwd<3>(sp, u, acc);
+            SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[4 + mu], sp);
+#pragma unroll
+            for (int k = 0; k < F::kWords; ++k) words[k] = lw[((4 + mu) * F::kWords + k) * 64 + lo];
+            link_decode<LP, RECON>(words, u);
+            if (mu == 0) hop_bwd<0>(sp, u, acc);
+            if (mu == 1) hop_bwd<1>(sp, u, acc);
+            if (mu == 2) hop_bwd<2>(sp, u, acc);
+            if (mu == 3) hop_bwd<3>(sp, u, acc);
+        }
+        const R b = (R)a.b_hop;
+        if (a.has_self) {
+            SpinorView vs = a.self[y];
+            vs.base += (int64_t)r * vs.rhs_bytes;
+            C<R> sf[12];
+            SpinorIO<SP>::load(vs, (int64_t)vs.site0 + i, sf);
+            const R as = (R)a.a_self;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = {as * sf[k].r + b * acc[k].r, as * sf[k].i + b * acc[k].i};
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = cscale(b, acc[k]);
+        }
+        if (a.gamma5) {
+#pragma unroll
+            for (int k = 6; k < 12; ++k) acc[k] = cneg(acc[k]);
+        }
+        const R c0 = (R)coef(a.c0);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = cscale(c0, acc[k]);
+        SpinorView vo = a.out[y];
+        vo.base += (int64_t)r * vo.rhs_bytes;
+        SpinorIO<SP>::store(vo, (int64_t)vo.site0 + i, acc);
+    }
+}
+
+template <int SP, int LP, int RECON>
+hipError_t launch_mrhs_fmt(const WilsonArgs& a, int ny, int nrhs, hipStream_t st) {
+    const dim3 grid((unsigned)((a.g.vh + 63) / 64), ny);
+    const size_t lds = (size_t)8 * LinkFmt<LP, RECON>::kWords * 64 * sizeof(uint32_t);
+    if (lds > 65536) {   // FP64 18-real links: 72 KiB of the 160 KiB per CU
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_wilson_mrhs<SP, LP, RECON>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_wilson_mrhs<SP, LP, RECON>), grid, dim3(256), lds, st, a, nrhs);
+    return hipGetLastError();
+}
+
 template <int SP, int LP, int RECON>
 hipError_t launch_fmt(const WilsonArgs& a, int ny, int block, hipStream_t st) {
     if (block == 0) {
@@ -365,6 +474,27 @@ hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& a, i
     }
 }
 
+hipError_t launch_wilson_mrhs(int sprec, int lprec, int recon, const WilsonArgs& a, int ny, int nrhs,
+                              hipStream_t st) {
+    const int key = sprec * 1000 + lprec * 100 + recon;
+    switch (key) {
+        case P64 * 1000 + P64 * 100 + 18: return launch_mrhs_fmt<P64, P64, 18>(a, ny, nrhs, st);
+        case P64 * 1000 + P64 * 100 + 12: return launch_mrhs_fmt<P64, P64, 12>(a, ny, nrhs, st);
+        case P64 * 1000 + P64 * 100 + 8: return launch_mrhs_fmt<P64, P64, 8>(a, ny, nrhs, st);
+        case P32 * 1000 + P32 * 100 + 18: return launch_mrhs_fmt<P32, P32, 18>(a, ny, nrhs, st);
+        case P32 * 1000 + P32 * 100 + 12: return launch_mrhs_fmt<P32, P32, 12>(a, ny, nrhs, st);
+        case P32 * 1000 + P32 * 100 + 8: return launch_mrhs_fmt<P32, P32, 8>(a, ny, nrhs, st);
+        case P32 * 1000 + P16 * 100 + 18: return launch_mrhs_fmt<P32, P16, 18>(a, ny, nrhs, st);
+        case P32 * 1000 + P16 * 100 + 12: return launch_mrhs_fmt<P32, P16, 12>(a, ny, nrhs, st);
+        case P16 * 1000 + P32 * 100 + 18: return launch_mrhs_fmt<P16, P32, 18>(a, ny, nrhs, st);
+        case P16 * 1000 + P32 * 100 + 12: return launch_mrhs_fmt<P16, P32, 12>(a, ny, nrhs, st);
+        case P16 * 1000 + P32 * 100 + 8: return launch_mrhs_fmt<P16, P32, 8>(a, ny, nrhs, st);
+        case P16 * 1000 + P16 * 100 + 18: return launch_mrhs_fmt<P16, P16, 18>(a, ny, nrhs, st);
+        case P16 * 1000 + P16 * 100 + 12: return launch_mrhs_fmt<P16, P16, 12>(a, ny, nrhs, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 WilsonArgs wilson_args(const ndq_geom* g, const ndq_gauge* U, int sprec) {
     WilsonArgs a;
     memset(&a, 0, sizeof(a));
@@ -391,7 +521,8 @@ int ndq_apply_Q(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spino
         return fail(NDQ_EINVAL, "ndq_apply_Q: in and out must share precision and nrhs");
     if (in->data == out->data) return fail(NDQ_EINVAL, "ndq_apply_Q: in and out must not alias");
     hipStream_t st = as_stream(stream);
-    for (int r = 0; r < in->nrhs; ++r) {
+    const bool batched = in->nrhs > 1;
+    for (int r = 0; r < (batched ? 1 : in->nrhs); ++r) {
         WilsonArgs a = wilson_args(g, U, in->prec);
         a.p0 = 0;
         for (int p = 0; p < 2; ++p) {
@@ -403,7 +534,8 @@ int ndq_apply_Q(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spino
         a.a_self = 4.0 + m;
         a.b_hop = -0.5;
         a.gamma5 = 1;
-        NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 2, tuning(in->prec, U->prec, U->recon).block, st));
+        if (batched) NDQ_HIP(launch_wilson_mrhs(in->prec, U->prec, U->recon, a, 2, in->nrhs, st));
+        else NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 2, tuning(in->prec, U->prec, U->recon).block, st));
     }
     return NDQ_OK;
 }
@@ -422,7 +554,8 @@ int ndq_apply_dslash(const ndq_geom* g, const ndq_gauge* U, const ndq_spinor* in
         return fail(NDQ_EINVAL, "ndq_apply_dslash: in and out must share precision and nrhs");
     hipStream_t st = as_stream(stream);
     const int p = out->parity;
-    for (int r = 0; r < in->nrhs; ++r) {
+    const bool batched = in->nrhs > 1;
+    for (int r = 0; r < (batched ? 1 : in->nrhs); ++r) {
         WilsonArgs a = wilson_args(g, U, in->prec);
         a.p0 = p;
         a.in[0] = view_of(g, in, 1 - p, r);
@@ -430,7 +563,8 @@ int ndq_apply_dslash(const ndq_geom* g, const ndq_gauge* U, const ndq_spinor* in
         a.has_self = 0;
         a.b_hop = 1.0;
         a.gamma5 = 0;
-        NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 1, tuning(in->prec, U->prec, U->recon).block, st));
+        if (batched) NDQ_HIP(launch_wilson_mrhs(in->prec, U->prec, U->recon, a, 1, in->nrhs, st));
+        else NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 1, tuning(in->prec, U->prec, U->recon).block, st));
     }
     return NDQ_OK;
 }

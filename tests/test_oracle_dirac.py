@@ -106,6 +106,55 @@ def test_gauge_covariance(dims):
     assert np.abs(lhs - rhs).max() < 1e-13
 
 
+class _Unit:
+    """Links U = 1 at every site of any lattice, indexable like a gauge field."""
+
+    def __getitem__(self, key):
+        sites, _ = key
+        return np.broadcast_to(np.eye(3, dtype=np.complex128), np.shape(sites) + (3, 3))
+
+
+def test_apply_Q_at_free_field_large():
+    """Per-site Q on the 32^3 x 64 lattice with U = 1 against the momentum-space closed form,
+    at sites on every face of the lattice and in its interior."""
+    dims = (64, 32, 32, 32)
+    rng = np.random.default_rng(5)
+    chi = rng.normal(size=(4, 3)) + 1j * rng.normal(size=(4, 3))
+    nvec = (5, 3, 11, 1)
+    p = 2 * np.pi * np.asarray(nvec) / np.asarray(dims)
+
+    def psi_at(idx):
+        x = np.stack(np.unravel_index(idx, dims), axis=-1)
+        return np.exp(1j * (x @ p))[:, None, None] * chi[None]
+
+    corners = np.array([[0, 0, 0, 0], [63, 31, 31, 31], [0, 31, 0, 31], [63, 0, 17, 0], [12, 5, 31, 0]])
+    sites = np.concatenate([geometry.lex_of(dims, corners), rng.integers(0, geometry.volume(dims), 64)])
+    _, g5 = dirac.gamma_matrices()
+    expect = np.einsum("st,vtc->vsc", g5 @ dirac.free_field_symbol(p, M), psi_at(sites))
+    got = dirac.apply_Q_at(_Unit(), psi_at, M, dims, sites)
+    assert np.abs(got - expect).max() < 1e-13
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 6, 2)])
+def test_apply_Q_at_gauge_covariance(dims):
+    """Per-site Q: Q[U^Omega](Omega psi)(y) = Omega(y) (Q[U] psi)(y) at every site, two right-hand sides."""
+    u = synthetic.gauge_field(dims)
+    v = geometry.volume(dims)
+    om = synthetic.haar_su3(v)
+    nb = geometry.neighbour_table(dims)
+    ug = np.einsum("vab,vmbc->vmac", om, u)
+    for mu in range(4):
+        ug[:, mu] = ug[:, mu] @ om[nb[:, mu]].conj().transpose(0, 2, 1)
+    psi = synthetic.spinor(v, nrhs=2)
+    psig = np.einsum("vab,rvsb->rvsa", om, psi)
+    sites = np.arange(v)
+    lhs = dirac.apply_Q_at(ug, lambda i: psig[:, i], M, dims, sites)
+    rhs = np.einsum("vab,rvsb->rvsa", om, dirac.apply_Q_at(u, lambda i: psi[:, i], M, dims, sites))
+    assert np.abs(lhs - rhs).max() < 1e-13
+    # and the per-site form agrees with the whole-lattice form
+    assert np.abs(dirac.apply_Q_at(u, lambda i: psi[:, i], M, dims, sites) - dirac.apply_Q(u, psi, M, dims)).max() < 1e-13
+
+
 def test_eo_schur_complement(dense_random):
     """Qhat_ee = gamma5 (D_ee - D_eo D_oo^{-1} D_oe), blocks taken from the dense D_W."""
     dims = dense_random.dims
