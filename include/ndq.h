@@ -134,6 +134,24 @@ int ndq_spinor_unpack(const ndq_geom* g, const ndq_spinor* src, void* d_canon, v
 int ndq_apply_Q(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in,
                 const ndq_spinor* out, void* stream);
 
+/* Q on several lattices in one persistent launch (batching of the stencil:
+ * uneven lattice sizes, each with its own links, mass and right-hand sides).
+ * Each job computes out = Q in exactly as ndq_apply_Q with nrhs > 1 does
+ * (links staged once per 64-site tile, every right-hand side of that tile
+ * computed from them), so its results equal that call's bit for bit (and, for
+ * nrhs = 1, those of the one-lane-per-site launch shape, block 64/128/256).
+ * All jobs share the spinor precision and the link format; 1 <= njobs <= 8;
+ * in, out: NDQ_FULL, same precision and nrhs, not aliased.  The grid fills the
+ * device once and walks the joint tile list.  Asynchronous. */
+typedef struct {
+    const ndq_geom* g;
+    const ndq_gauge* U;
+    double m;
+    const ndq_spinor* in;
+    const ndq_spinor* out;
+} ndq_q_job;
+int ndq_apply_Q_multi(const ndq_q_job* jobs, int32_t njobs, void* stream);
+
 /* Even/odd hopping block: out_p = H_{p,1-p} in, where D_W = (4+m) - H/2 and
  * H psi(x) = sum_{mu=+-0..+-3} U_mu(x)(1-gamma_mu) psi(x+mu) (Eq. 1, Eq. 2).
  * `in` has parity 1-p, `out` parity p (both NDQ_EVEN/NDQ_ODD); 1320 flop per
@@ -182,6 +200,9 @@ typedef struct {
     double tol;               /* rational approximant: multi-shift CG relative residual       */
     int32_t max_iter;         /* rational approximant: CG iteration limit                     */
     int32_t check_every;      /* rational approximant: convergence read-back interval (>= 1)  */
+    int32_t graph;            /* rational approximant: nonzero launches each block of
+                                 check_every multi-shift iterations as one captured HIP graph
+                                 (same kernels and arguments as the eager launches)           */
 } ndq_overlap_params;
 
 typedef struct {
@@ -321,6 +342,24 @@ int ndq_set_launch(int block, int xcd_remap);
 /* The same for one storage format only (spinor precision, link precision,
  * recon); the autotuner records its choice per format this way. */
 int ndq_set_launch_for(int sprec, int lprec, int recon, int block, int xcd_remap);
+
+/* Autotuner of the launch shape: times `reps` even/odd dslash applies on
+ * lattice g with links U and spinors of precision sprec for each launch shape
+ * (block 0/64/128/256, XCD remap off/on), on ceil(rotate_bytes / set size)
+ * rotating copies of (links, even spinor, odd spinor) so that consecutive
+ * applies stream from HBM as in a solver (rotate_bytes <= 0: one set), and
+ * records the fastest shape for that storage format as ndq_set_launch_for
+ * does.  Allocates and frees its own device buffers; synchronises `stream`.
+ * Errors: NDQ_EINVAL, NDQ_EPREC, NDQ_EHIP (the previous shape is kept). */
+typedef struct {
+    int32_t block;        /* chosen shape                                            */
+    int32_t xcd_remap;
+    double us_best;       /* its average time per dslash, microseconds               */
+    double us[8];         /* every shape: index 2 * b + xcd_remap, b over 0/64/128/256 */
+    int32_t nsets;        /* rotating sets used                                      */
+} ndq_tune_result;
+int ndq_autotune(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, int64_t rotate_bytes,
+                 ndq_tune_result* out, void* stream);
 
 /* ---- diagnostics -------------------------------------------------------- */
 const char* ndq_last_error(void);

@@ -1,6 +1,7 @@
 // Internal interfaces of the sign-function, D_N and solver layers.
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "ndq_internal.h"
@@ -131,5 +132,10 @@ int apply_sign(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* 
 int q_combo(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in, const ndq_spinor* out,
             Coef c0, int nv, const ndq_spinor* const* v, const Coef* cv, double* partials, hipStream_t st);
 int q_blocks(const ndq_geom* g, const ndq_gauge* U, int sprec);
+
+// Records the kernel launches `body` makes on the stream it is given into a HIP
+// graph and launches the graph on `st` (kept instantiated graphs are refreshed
+// with hipGraphExecUpdate).  `body` must launch kernels only.
+int launch_captured(const std::function<int(hipStream_t)>& body, hipStream_t st);
 
 }  // namespace ndq

@@ -10,7 +10,8 @@
 //    2n + 1 applications of Q, no reductions, no host synchronisation;
 //  * rational, sign ~ X sum_l beta_l (X^2 + sigma_l)^{-1}, by multi-shift CG
 //    with all scalars on the device; the host only reads the state every
-//    `check_every` iterations.
+//    `check_every` iterations.  Optionally each block of `check_every`
+//    iterations is launched as one captured HIP graph.
 #include <math.h>
 #include <string.h>
 
@@ -167,21 +168,47 @@ int rational_apply(const ndq_geom* g, const ndq_gauge* U, double m, const Approx
     const int max_iter = p->max_iter > 0 ? p->max_iter : 100000;
     const int every = p->check_every > 0 ? p->check_every : 8;
     ndq_spinor p0 = P;   // base shift sigma_0 (smallest)
+    // one CG iteration for all shifts: two stencil launches, the scalar
+    // recurrences on the device and the fused vector update
+    auto iteration = [&](bool first, hipStream_t s) -> int {
+        int e;
+        if ((e = q_combo(g, U, m, &p0, &t, host(1.0), 0, nullptr, nullptr, sc.part_tt, s))) return e;
+        if ((e = ms_alpha(sc.ms, k, sc.part_tt, nq, first ? nullptr : sc.part_pp, nl, s))) return e;
+        // r <- r - alpha (X^2 + sigma_0) p_0 = (-alpha/lam^2) Q t + r - alpha sigma_0 p_0
+        const ndq_spinor* v[2] = {&r, &p0};
+        const Coef cv[2] = {host(1.0), Coef{1.0, &sc.ms->cp}};
+        if ((e = q_combo(g, U, m, &t, &r, Coef{1.0, &sc.ms->c0}, 2, v, cv, sc.part_rr, s))) return e;
+        if ((e = ms_beta(sc.ms, k, sc.part_rr, nq, s))) return e;
+        return ms_update(g, prec, sc.ms, k, &r, &y, &P, sc.part_pp, s);
+    };
     MsState hs;
     int it = 0;
     bool done = false;
+    if (p->graph) {
+        // the first iteration differs (no previous search direction); the
+        // following blocks of `every` iterations are one captured graph each
+        if ((rc = iteration(true, st))) return rc;
+        *qcount += 2;
+        ++it;
+    }
     while (!done) {
-        for (int c = 0; c < every; ++c) {
-            if ((rc = q_combo(g, U, m, &p0, &t, host(1.0), 0, nullptr, nullptr, sc.part_tt, st))) return rc;
-            if ((rc = ms_alpha(sc.ms, k, sc.part_tt, nq, it == 0 ? nullptr : sc.part_pp, nl, st))) return rc;
-            // r <- r - alpha (X^2 + sigma_0) p_0 = (-alpha/lam^2) Q t + r - alpha sigma_0 p_0
-            const ndq_spinor* v[2] = {&r, &p0};
-            const Coef cv[2] = {host(1.0), Coef{1.0, &sc.ms->cp}};
-            if ((rc = q_combo(g, U, m, &t, &r, Coef{1.0, &sc.ms->c0}, 2, v, cv, sc.part_rr, st))) return rc;
-            if ((rc = ms_beta(sc.ms, k, sc.part_rr, nq, st))) return rc;
-            if ((rc = ms_update(g, prec, sc.ms, k, &r, &y, &P, sc.part_pp, st))) return rc;
-            *qcount += 2;
-            ++it;
+        if (p->graph) {
+            rc = launch_captured([&](hipStream_t s) -> int {
+                for (int c = 0; c < every; ++c) {
+                    const int e = iteration(false, s);
+                    if (e) return e;
+                }
+                return NDQ_OK;
+            }, st);
+            if (rc) return rc;
+            *qcount += 2 * every;
+            it += every;
+        } else {
+            for (int c = 0; c < every; ++c) {
+                if ((rc = iteration(it == 0, st))) return rc;
+                *qcount += 2;
+                ++it;
+            }
         }
         NDQ_HIP(hipMemcpyAsync(&hs, sc.ms, sizeof(MsState), hipMemcpyDeviceToHost, st));
         NDQ_HIP(hipStreamSynchronize(st));

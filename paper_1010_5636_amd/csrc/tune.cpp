@@ -1,0 +1,128 @@
+// Launch-shape autotuner of the stencil: times the even/odd dslash of one
+// storage format on one lattice for every launch shape (one lane per site with
+// 64/128/256-lane workgroups, or the direction split) with and without the
+// XCD remap, and records the fastest for that format (ndq_set_launch_for).
+#include <string.h>
+
+#include <vector>
+
+#include "ndq_internal.h"
+#include "wilson.h"
+
+using namespace ndq;
+
+namespace {
+
+const int kBlocks[4] = {0, 64, 128, 256};
+
+struct Set {
+    void* links = nullptr;
+    void* even = nullptr;
+    void* odd = nullptr;
+};
+
+}  // namespace
+
+extern "C" int ndq_autotune(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, int64_t rotate_bytes,
+                            ndq_tune_result* out, void* stream) {
+    if (!g || !out) return fail(NDQ_EINVAL, "ndq_autotune: NULL argument");
+    int rc = check_gauge(U);
+    if (rc) return rc;
+    if (sprec < NDQ_F64 || sprec > NDQ_F16) return fail(NDQ_EPREC, "ndq_autotune: bad spinor precision %d", sprec);
+    if ((sprec == NDQ_F64) != (U->prec == NDQ_F64))
+        return fail(NDQ_EPREC, "ndq_autotune: F64 spinors go with F64 links, F32/F16 with F32/F16");
+    if (reps < 1) return fail(NDQ_EINVAL, "ndq_autotune: reps must be >= 1");
+    hipStream_t st = as_stream(stream);
+    const size_t lb = ndq_gauge_bytes(g, U->prec, U->recon);
+    const size_t sb = (size_t)spinor_rhs_bytes(g, sprec, NDQ_EVEN);
+    const size_t set_bytes = lb + 2 * sb;
+    int nsets = rotate_bytes > 0 ? (int)((rotate_bytes + (int64_t)set_bytes - 1) / (int64_t)set_bytes) : 1;
+    nsets = std::max(1, std::min(nsets, 256));
+    std::vector<Set> sets(nsets);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const Tuning saved = tuning(sprec, U->prec, U->recon);
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        for (Set& s : sets) {
+            if (s.links && s.links != U->data) (void)hipFree(s.links);
+            if (s.even) (void)hipFree(s.even);
+            if (s.odd) (void)hipFree(s.odd);
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    auto hip_fail = [&](hipError_t e, const char* what) {
+        cleanup();
+        tuning(sprec, U->prec, U->recon) = saved;
+        return fail(NDQ_EHIP, "ndq_autotune: %s: %s", what, hipGetErrorString(e));
+    };
+    hipError_t e;
+    for (int k = 0; k < nsets; ++k) {
+        if (k == 0) {
+            sets[k].links = U->data;
+        } else {
+            if ((e = hipMalloc(&sets[k].links, lb)) != hipSuccess) return hip_fail(e, "hipMalloc");
+            if ((e = hipMemcpyAsync(sets[k].links, U->data, lb, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+                return hip_fail(e, "copy of the links");
+        }
+        if ((e = hipMalloc(&sets[k].even, sb)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMalloc(&sets[k].odd, sb)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        // any finite pattern: 0x3c00 halves (1.0 in F16), a small number in F32/F64
+        if ((e = hipMemsetD32Async(sets[k].even, 0x3c003c00u, sb / 4, st)) != hipSuccess) return hip_fail(e, "fill");
+        if ((e = hipMemsetD32Async(sets[k].odd, 0x3c003c00u, sb / 4, st)) != hipSuccess) return hip_fail(e, "fill");
+    }
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+        return hip_fail(e, "hipEventCreate");
+    auto launch = [&](int k) -> int {
+        const Set& s = sets[k % nsets];
+        const int p = (k / nsets) & 1;   // alternate D_eo and D_oe
+        ndq_gauge u = *U;
+        u.data = s.links;
+        ndq_spinor in{p ? s.odd : s.even, sprec, p ? NDQ_ODD : NDQ_EVEN, 1};
+        ndq_spinor o{p ? s.even : s.odd, sprec, p ? NDQ_EVEN : NDQ_ODD, 1};
+        return ndq_apply_dslash(g, &u, &in, &o, stream);
+    };
+    memset(out, 0, sizeof(*out));
+    double best = 1e300;
+    int best_b = 0, best_x = 1;
+    for (int b = 0; b < 4; ++b) {
+        for (int x = 0; x < 2; ++x) {
+            Tuning& t = tuning(sprec, U->prec, U->recon);
+            t.block = kBlocks[b];
+            t.xcd_remap = x;
+            for (int k = 0; k < std::min(8, 2 * nsets); ++k)
+                if ((rc = launch(k))) {
+                    cleanup();
+                    tuning(sprec, U->prec, U->recon) = saved;
+                    return rc;
+                }
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            for (int k = 0; k < reps; ++k)
+                if ((rc = launch(k))) {
+                    cleanup();
+                    tuning(sprec, U->prec, U->recon) = saved;
+                    return rc;
+                }
+            if ((e = hipEventRecord(e1, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+            const double us = 1e3 * ms / reps;
+            out->us[2 * b + x] = us;
+            if (us < best) {
+                best = us;
+                best_b = kBlocks[b];
+                best_x = x;
+            }
+        }
+    }
+    cleanup();
+    Tuning& t = tuning(sprec, U->prec, U->recon);
+    t.block = best_b;
+    t.xcd_remap = best_x;
+    out->block = best_b;
+    out->xcd_remap = best_x;
+    out->us_best = best;
+    out->nsets = nsets;
+    return NDQ_OK;
+}

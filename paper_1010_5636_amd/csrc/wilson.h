@@ -25,6 +25,26 @@ struct WilsonArgs {
     int xcd_remap;
 };
 
+// One lattice of a persistent multi-lattice launch of Q (NDQ_FULL fields):
+// views per output parity y address right-hand side 0.
+constexpr int kMaxJobs = 8;
+struct QJob {
+    GeomK g;
+    const char* links;
+    SpinorView in[2];     // parity 1 - y
+    SpinorView self[2];   // parity y
+    SpinorView out[2];    // parity y
+    double a_self;        // 4 + m
+    int nrhs;
+    int tile0;            // first tile of this lattice in the joint list
+    int tiles;            // tiles of 64 sites per parity
+};
+struct MultiArgs {
+    QJob job[kMaxJobs];
+    int njobs;
+    int total;            // tiles over all lattices and both parities
+};
+
 // Launch shape of the stencil: block = 64/128/256 lanes with one lane per
 // site, or 0 for the direction-split form; xcd_remap as in ndq_set_launch.
 struct Tuning {
@@ -41,6 +61,7 @@ int wilson_blocks(const ndq_geom* g, int block, int ny);
 hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& a, int ny, int block, hipStream_t st);
 // nrhs right-hand sides (a.in/out/self views point at rhs 0; rhs r at + r * rhs_bytes),
 // links staged once in LDS; epilogue without extra vectors or partial sums.
+hipError_t launch_wilson_multi(int sprec, int lprec, int recon, const MultiArgs& a, hipStream_t st);
 hipError_t launch_wilson_mrhs(int sprec, int lprec, int recon, const WilsonArgs& a, int ny, int nrhs, hipStream_t st);
 
 }  // namespace ndq

@@ -14,6 +14,10 @@
 // Chiral basis: gamma_mu = [[0, A_mu], [A_mu^H, 0]], A_0 = -1, A_k = -i sigma_k,
 // so (1 - gamma_mu) psi = (h, -A^H h) with h = psi_up - A psi_dn, and
 // (1 + gamma_mu) psi = (g, A^H g) with g = psi_up + A psi_dn.
+#include <string.h>
+
+#include <algorithm>
+
 #include "wilson.h"
 
 using namespace ndq;
@@ -327,29 +331,32 @@ __global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
 // wavefront is one right-hand side's 64 consecutive sites.  The per-site
 // arithmetic is that of k_wilson (same hop order and epilogue), so results
 // match the one-lane-per-site kernel bit for bit.
+//
+// One tile: output parity p, sites 64*tile .. 64*tile+63 of that parity.  The
+// views address right-hand side 0; right-hand side r sits r * rhs_bytes
+// further.  `self` may be null (no same-site term).  Must be reached by all
+// 256 threads of the workgroup (it synchronises once).
 template <int SP, int LP, int RECON>
-__global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, int nrhs) {
+__device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int p, int32_t tile,
+                                          const SpinorView& in, const SpinorView* self, const SpinorView& out,
+                                          double a_self, double b_hop, int gamma5, double c0d, int nrhs,
+                                          uint32_t* lw) {
     using R = typename SpinorIO<SP>::R;
     using F = LinkFmt<LP, RECON>;
-    extern __shared__ uint32_t lw[];   // [8 dirs][F::kWords][64 sites]
-    unsigned lin = blockIdx.y * gridDim.x + blockIdx.x;
-    if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x * gridDim.y);
-    const int y = (int)(lin / gridDim.x);
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int32_t i = (int32_t)(lin - (unsigned)y * gridDim.x) * 64 + lane;
-    const int p = a.p0 + y;
-    const bool active = i < a.g.vh;
+    const int32_t i = tile * 64 + lane;
+    const bool active = i < g.vh;
     int32_t nb[8];
     if (active) {
-        const SiteCoord x = eo_coords(a.g, p, i);
-        eo_neighbours(a.g, i, x, nb);
+        const SiteCoord x = eo_coords(g, p, i);
+        eo_neighbours(g, i, x, nb);
         // wavefront w stages the forward link mu = w and the backward link mu = w
         uint32_t words[F::kWords];
-        link_load_words<LP, RECON>(a.links, a.g.vh, p * 4 + w, i, words);
+        link_load_words<LP, RECON>(links, g.vh, p * 4 + w, i, words);
 #pragma unroll
         for (int k = 0; k < F::kWords; ++k) lw[(w * F::kWords + k) * 64 + lane] = words[k];
-        link_load_words<LP, RECON>(a.links, a.g.vh, (1 - p) * 4 + w, nb[4 + w], words);
+        link_load_words<LP, RECON>(links, g.vh, (1 - p) * 4 + w, nb[4 + w], words);
 #pragma unroll
         for (int k = 0; k < F::kWords; ++k) lw[((4 + w) * F::kWords + k) * 64 + lane] = words[k];
     }
@@ -361,7 +368,7 @@ __global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, int nrhs) {
         // them be hoisted into registers (which would cost occupancy)
         int lo = lane;
         asm volatile("" : "+v"(lo));
-        SpinorView vin = a.in[y];
+        SpinorView vin = in;
         vin.base += (int64_t)r * vin.rhs_bytes;
         C<R> acc[12];
 #pragma unroll
@@ -388,42 +395,106 @@ __global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, int nrhs) {
             if (mu == 2) hop_bwd<2>(sp, u, acc);
             if (mu == 3) hop_bwd<3>(sp, u, acc);
         }
-        const R b = (R)a.b_hop;
-        if (a.has_self) {
-            SpinorView vs = a.self[y];
+        const R b = (R)b_hop;
+        if (self) {
+            SpinorView vs = *self;
             vs.base += (int64_t)r * vs.rhs_bytes;
             C<R> sf[12];
             SpinorIO<SP>::load(vs, (int64_t)vs.site0 + i, sf);
-            const R as = (R)a.a_self;
+            const R as = (R)a_self;
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = {as * sf[k].r + b * acc[k].r, as * sf[k].i + b * acc[k].i};
         } else {
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = cscale(b, acc[k]);
         }
-        if (a.gamma5) {
+        if (gamma5) {
 #pragma unroll
             for (int k = 6; k < 12; ++k) acc[k] = cneg(acc[k]);
         }
-        const R c0 = (R)coef(a.c0);
+        const R c0 = (R)c0d;
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = cscale(c0, acc[k]);
-        SpinorView vo = a.out[y];
+        SpinorView vo = out;
         vo.base += (int64_t)r * vo.rhs_bytes;
         SpinorIO<SP>::store(vo, (int64_t)vo.site0 + i, acc);
     }
 }
 
 template <int SP, int LP, int RECON>
+__global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, int nrhs) {
+    extern __shared__ uint32_t lw[];   // [8 dirs][link words][64 sites]
+    unsigned lin = blockIdx.y * gridDim.x + blockIdx.x;
+    if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x * gridDim.y);
+    const int y = (int)(lin / gridDim.x);
+    const int32_t tile = (int32_t)(lin - (unsigned)y * gridDim.x);
+    mrhs_tile<SP, LP, RECON>(a.g, a.links, a.p0 + y, tile, a.in[y], a.has_self ? &a.self[y] : nullptr, a.out[y],
+                             a.a_self, a.b_hop, a.gamma5, coef(a.c0), nrhs, lw);
+}
+
+template <int SP, int LP, int RECON>
+size_t mrhs_lds_bytes() {
+    return (size_t)8 * LinkFmt<LP, RECON>::kWords * 64 * sizeof(uint32_t);
+}
+
+// FP64 18-real links need 72 KiB of LDS per workgroup (of the 160 KiB per CU):
+// opt in above the default 64 KiB limit.
+template <typename K>
+hipError_t allow_lds(K kernel, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+template <int SP, int LP, int RECON>
 hipError_t launch_mrhs_fmt(const WilsonArgs& a, int ny, int nrhs, hipStream_t st) {
     const dim3 grid((unsigned)((a.g.vh + 63) / 64), ny);
-    const size_t lds = (size_t)8 * LinkFmt<LP, RECON>::kWords * 64 * sizeof(uint32_t);
-    if (lds > 65536) {   // FP64 18-real links: 72 KiB of the 160 KiB per CU
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_wilson_mrhs<SP, LP, RECON>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    const size_t lds = mrhs_lds_bytes<SP, LP, RECON>();
+    const hipError_t e = allow_lds(&k_wilson_mrhs<SP, LP, RECON>, lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_wilson_mrhs<SP, LP, RECON>), grid, dim3(256), lds, st, a, nrhs);
+    return hipGetLastError();
+}
+
+// Q on several lattices (each with its own links and right-hand sides) in one
+// persistent launch: the tiles of all lattices (both output parities) form one
+// list; a grid that fills the device once walks it, workgroup b taking one
+// contiguous chunk of tiles (chunks adjacent in the list go to workgroups on
+// the same XCD), and each tile runs mrhs_tile with the epilogue of Q.
+template <int SP, int LP, int RECON>
+__global__ void __launch_bounds__(256) k_wilson_multi(MultiArgs a) {
+    extern __shared__ uint32_t lw[];
+    const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int chunk = (a.total + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int t0 = (int)lin * chunk;
+    const int t1 = min(a.total, t0 + chunk);
+    for (int t = t0; t < t1; ++t) {
+        int j = 0;
+        while (j + 1 < a.njobs && t >= a.job[j + 1].tile0) ++j;
+        const QJob& J = a.job[j];
+        const int local = t - J.tile0;
+        const int y = local / J.tiles;
+        const int32_t tile = local - y * J.tiles;
+        mrhs_tile<SP, LP, RECON>(J.g, J.links, y, tile, J.in[y], &J.self[y], J.out[y], J.a_self, -0.5, 1, 1.0,
+                                 J.nrhs, lw);
+        __syncthreads();   // the next tile overwrites the staged links
+    }
+}
+
+template <int SP, int LP, int RECON>
+hipError_t launch_multi_fmt(const MultiArgs& a, hipStream_t st) {
+    const size_t lds = mrhs_lds_bytes<SP, LP, RECON>();
+    auto kernel = &k_wilson_multi<SP, LP, RECON>;
+    hipError_t e = allow_lds(kernel, lds);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), 256, lds)) !=
+        hipSuccess)
+        return e;
+    const int grid = std::max(1, std::min(a.total, std::max(1, per_cu) * cus));
+    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(256), lds, st, a);
     return hipGetLastError();
 }
 
@@ -495,6 +566,26 @@ hipError_t launch_wilson_mrhs(int sprec, int lprec, int recon, const WilsonArgs&
     }
 }
 
+hipError_t launch_wilson_multi(int sprec, int lprec, int recon, const MultiArgs& a, hipStream_t st) {
+    const int key = sprec * 1000 + lprec * 100 + recon;
+    switch (key) {
+        case P64 * 1000 + P64 * 100 + 18: return launch_multi_fmt<P64, P64, 18>(a, st);
+        case P64 * 1000 + P64 * 100 + 12: return launch_multi_fmt<P64, P64, 12>(a, st);
+        case P64 * 1000 + P64 * 100 + 8: return launch_multi_fmt<P64, P64, 8>(a, st);
+        case P32 * 1000 + P32 * 100 + 18: return launch_multi_fmt<P32, P32, 18>(a, st);
+        case P32 * 1000 + P32 * 100 + 12: return launch_multi_fmt<P32, P32, 12>(a, st);
+        case P32 * 1000 + P32 * 100 + 8: return launch_multi_fmt<P32, P32, 8>(a, st);
+        case P32 * 1000 + P16 * 100 + 18: return launch_multi_fmt<P32, P16, 18>(a, st);
+        case P32 * 1000 + P16 * 100 + 12: return launch_multi_fmt<P32, P16, 12>(a, st);
+        case P16 * 1000 + P32 * 100 + 18: return launch_multi_fmt<P16, P32, 18>(a, st);
+        case P16 * 1000 + P32 * 100 + 12: return launch_multi_fmt<P16, P32, 12>(a, st);
+        case P16 * 1000 + P32 * 100 + 8: return launch_multi_fmt<P16, P32, 8>(a, st);
+        case P16 * 1000 + P16 * 100 + 18: return launch_multi_fmt<P16, P16, 18>(a, st);
+        case P16 * 1000 + P16 * 100 + 12: return launch_multi_fmt<P16, P16, 12>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 WilsonArgs wilson_args(const ndq_geom* g, const ndq_gauge* U, int sprec) {
     WilsonArgs a;
     memset(&a, 0, sizeof(a));
@@ -537,6 +628,52 @@ int ndq_apply_Q(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spino
         if (batched) NDQ_HIP(launch_wilson_mrhs(in->prec, U->prec, U->recon, a, 2, in->nrhs, st));
         else NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 2, tuning(in->prec, U->prec, U->recon).block, st));
     }
+    return NDQ_OK;
+}
+
+int ndq_apply_Q_multi(const ndq_q_job* jobs, int32_t njobs, void* stream) {
+    if (!jobs || njobs < 1 || njobs > kMaxJobs)
+        return fail(NDQ_EINVAL, "ndq_apply_Q_multi: need 1..%d jobs (got %d)", kMaxJobs, njobs);
+    MultiArgs a;
+    memset(&a, 0, sizeof(a));
+    a.njobs = njobs;
+    int64_t total = 0;
+    int sprec = -1, lprec = -1, recon = -1;
+    for (int j = 0; j < njobs; ++j) {
+        const ndq_q_job& J = jobs[j];
+        if (!J.g) return fail(NDQ_EINVAL, "ndq_apply_Q_multi: job %d: NULL geometry", j);
+        int rc = check_gauge(J.U);
+        if (!rc) rc = check_spinor(J.g, J.in, NDQ_FULL, "ndq_apply_Q_multi in");
+        if (!rc) rc = check_spinor(J.g, J.out, NDQ_FULL, "ndq_apply_Q_multi out");
+        if (!rc) rc = check_pair(J.U, J.in);
+        if (rc) return rc;
+        if (J.in->prec != J.out->prec || J.in->nrhs != J.out->nrhs)
+            return fail(NDQ_EINVAL, "ndq_apply_Q_multi: job %d: in and out must share precision and nrhs", j);
+        if (J.in->data == J.out->data) return fail(NDQ_EINVAL, "ndq_apply_Q_multi: job %d: in and out alias", j);
+        if (j == 0) {
+            sprec = J.in->prec;
+            lprec = J.U->prec;
+            recon = J.U->recon;
+        } else if (J.in->prec != sprec || J.U->prec != lprec || J.U->recon != recon) {
+            return fail(NDQ_EINVAL, "ndq_apply_Q_multi: job %d: all jobs must share spinor precision and link format", j);
+        }
+        QJob& q = a.job[j];
+        q.g = J.g->k;
+        q.links = static_cast<const char*>(J.U->data);
+        for (int p = 0; p < 2; ++p) {
+            q.in[p] = view_of(J.g, J.in, 1 - p, 0);
+            q.self[p] = view_of(J.g, J.in, p, 0);
+            q.out[p] = view_of(J.g, J.out, p, 0);
+        }
+        q.a_self = 4.0 + J.m;
+        q.nrhs = J.in->nrhs;
+        q.tiles = (J.g->vh + 63) / 64;
+        q.tile0 = (int)total;
+        total += 2 * (int64_t)q.tiles;
+    }
+    if (total > INT32_MAX) return fail(NDQ_EINVAL, "ndq_apply_Q_multi: too many sites");
+    a.total = (int)total;
+    NDQ_HIP(launch_wilson_multi(sprec, lprec, recon, a, as_stream(stream)));
     return NDQ_OK;
 }
 

@@ -44,11 +44,21 @@ class _Spinor(ctypes.Structure):
                 ("nrhs", ctypes.c_int32)]
 
 
+class _QJob(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("U", ctypes.POINTER(_Gauge)), ("m", ctypes.c_double),
+                ("inp", ctypes.POINTER(_Spinor)), ("out", ctypes.POINTER(_Spinor))]
+
+
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("us_best", ctypes.c_double),
+                ("us", ctypes.c_double * 8), ("nsets", ctypes.c_int32)]
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("m", ctypes.c_double), ("mq", ctypes.c_double), ("lam_max", ctypes.c_double),
                 ("approx", ctypes.c_void_p), ("modes", ctypes.c_void_p), ("nu", ctypes.POINTER(ctypes.c_double)),
                 ("nev", ctypes.c_int32), ("form", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -98,6 +108,9 @@ _SIG = {
     "ndq_spinor_pack": (_I, [_P, _P, ctypes.POINTER(_Spinor), _P]),
     "ndq_spinor_unpack": (_I, [_P, ctypes.POINTER(_Spinor), _P, _P]),
     "ndq_apply_Q": (_I, [_P, ctypes.POINTER(_Gauge), _D, ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P]),
+    "ndq_autotune": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                          ctypes.POINTER(_TuneResult), _P]),
+    "ndq_apply_Q_multi": (_I, [ctypes.POINTER(_QJob), ctypes.c_int32, _P]),
     "ndq_apply_dslash": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P]),
     "ndq_apply_Qhat_ee": (_I, [_P, ctypes.POINTER(_Gauge), _D, ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor),
                                ctypes.POINTER(_Spinor), _P]),
@@ -169,6 +182,15 @@ def version() -> str:
 def set_launch(block: int, xcd_remap: bool = True):
     """Launch shape for every storage format (block 0 = direction split)."""
     _check(lib().ndq_set_launch(block, int(bool(xcd_remap))))
+
+
+def autotune(geom: "Geometry", U: "GaugeField", sprec: int, reps: int = 100, rotate_bytes: int = 0, stream=None) -> dict:
+    """Time every stencil launch shape for this format and keep the fastest."""
+    r = _TuneResult()
+    _check(lib().ndq_autotune(geom.handle, ctypes.byref(U.desc), int(sprec), int(reps), int(rotate_bytes),
+                              ctypes.byref(r), _stream(stream)))
+    shapes = {f"block{b}_xcd{x}": r.us[2 * i + x] for i, b in enumerate((0, 64, 128, 256)) for x in (0, 1)}
+    return {"block": r.block, "xcd_remap": r.xcd_remap, "us_best": r.us_best, "us": shapes, "nsets": r.nsets}
 
 
 def set_launch_for(sprec: int, lprec: int, recon: int, block: int, xcd_remap: bool = True):
@@ -279,6 +301,16 @@ def apply_Q(geom: Geometry, U: GaugeField, m: float, inp: SpinorField, out: Spin
                              ctypes.byref(out.desc), _stream(stream)))
 
 
+def apply_Q_multi(jobs, stream=None):
+    """Q on several lattices in one persistent launch: ``jobs`` is a list of
+    (geom, U, m, inp, out) tuples (NDQ_FULL fields, shared formats)."""
+    arr = (_QJob * len(jobs))()
+    for k, (geom, U, m, inp, out) in enumerate(jobs):
+        arr[k] = _QJob(geom.handle, ctypes.pointer(U.desc), float(m), ctypes.pointer(inp.desc),
+                       ctypes.pointer(out.desc))
+    _check(lib().ndq_apply_Q_multi(arr, len(jobs), _stream(stream)))
+
+
 def apply_dslash(geom: Geometry, U: GaugeField, inp: SpinorField, out: SpinorField, stream=None):
     _check(lib().ndq_apply_dslash(geom.handle, ctypes.byref(U.desc), ctypes.byref(inp.desc),
                                   ctypes.byref(out.desc), _stream(stream)))
@@ -340,7 +372,7 @@ class Overlap:
 
     def __init__(self, geom: Geometry, m: float, approx: Approx, lam_max: float, modes: "SpinorField | None" = None,
                  nu=None, mq: float = 0.0, form: int = LITERAL, tol: float = 1e-12, max_iter: int = 100000,
-                 check_every: int = 8):
+                 check_every: int = 8, graph: bool = False):
         import numpy as np
         self.geom, self.approx, self.modes = geom, approx, modes
         nev = 0 if modes is None else modes.nrhs
@@ -350,7 +382,7 @@ class Overlap:
         self.p = _Params(float(m), float(mq), float(lam_max), approx.handle.value,
                          None if modes is None else modes.buf.data_ptr(),
                          self.nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nev, form, float(tol),
-                         int(max_iter), int(check_every))
+                         int(max_iter), int(check_every), int(bool(graph)))
         self._ws = {}
 
     def workspace(self, prec: int, op: int):
