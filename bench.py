@@ -50,7 +50,14 @@ def bytes_per_site(sp, lp, recon):
     return 8 * recon * LINK_REAL_BYTES[lp] + 2 * SPINOR_BYTES[sp]
 
 
-def read_traffic(fmt_name):
+def kernel_name(launch):
+    """Name of the dslash kernel that the launch shape selects (as rocprofv3 lists it)."""
+    if launch["block"] == 0:
+        return "k_wilson_dirsplit (even/odd dslash, 4 wavefronts per 64 sites)"
+    return f"k_wilson (even/odd dslash, {launch['block']}-lane workgroups)"
+
+
+def read_traffic(fmt_name, launch):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "dslash_16c32_traffic.json")
@@ -65,7 +72,9 @@ def read_traffic(fmt_name):
     if rec.get("kernel_hash") != kernel_hash():
         return None
     ent = rec.get("formats", {}).get(fmt_name)
-    return None if ent is None else ent.get("bytes_per_launch")
+    if ent is None or ent.get("launch") != launch:
+        return None
+    return ent.get("bytes_per_launch")
 
 
 def cpu_baseline(max_seconds=20.0):
@@ -175,6 +184,197 @@ def solve_leg(log):
     return out
 
 
+def _time_events(fn, reps):
+    """Average milliseconds of fn() over reps calls between two events on the current stream."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+BATCH_DIMS = (64, 32, 32, 32)
+MULTI_DIMS = [(8, 8, 8, 8), (12, 12, 12, 12), (32, 16, 16, 16)]
+
+
+def batch_leg(log):
+    """Batching of the stencil.
+    (i) The 12 spin-colour point sources on 32^3 x 64 with FP32 spinors and
+        18-real FP32 links: one multi-RHS Q apply (links staged once per tile)
+        against 12 single-RHS applies of the same data.  Algorithmic bytes per
+        site: 12 x (96 in + 96 out) + 4 x 72 links = 2592 batched, 12 x 480 single.
+    (ii) One persistent launch of Q over 8^4 + 12^4 + 16^3x32 at 4 RHS each
+        (F32 spinors, 12-real links; 155904 sites x (4 x 192 + 4 x 48) B) against
+        the three lattices launched one after the other, on 3 rotating copies."""
+    import torch
+    import synthetic
+    import paper_1010_5636_amd as ndq
+    dev = torch.device("cuda")
+    out = {}
+    t0 = time.perf_counter()
+    g = ndq.Geometry(BATCH_DIMS)
+    v = g.volume
+    u = torch.from_numpy(synthetic.gauge_field(BATCH_DIMS)).to(dev)
+    U = ndq.GaugeField.pack(g, u, ndq.F32, 18)
+    del u
+    canon = torch.zeros((12, v, 4, 3), dtype=torch.complex128, device=dev)
+    for s in range(4):
+        for c in range(3):
+            canon[3 * s + c, 0, s, c] = 1.0
+    x = ndq.SpinorField.pack(g, canon, ndq.F32, ndq.FULL)
+    del canon
+    y = x.like()
+    rb = g.spinor_bytes(ndq.F32, ndq.FULL, 1)
+    xs = [ndq.SpinorField(g, ndq.F32, ndq.FULL, 1, buffer=x.buf[r * rb:(r + 1) * rb]) for r in range(12)]
+    ys = [ndq.SpinorField(g, ndq.F32, ndq.FULL, 1, buffer=y.buf[r * rb:(r + 1) * rb]) for r in range(12)]
+    torch.cuda.synchronize()
+    log(f"batch leg: 32^3x64 fields {time.perf_counter() - t0:.1f} s")
+
+    def batched():
+        ndq.apply_Q(g, U, M, x, y)
+
+    def singles():
+        for r in range(12):
+            ndq.apply_Q(g, U, M, xs[r], ys[r])
+
+    batched()
+    singles()
+    ms_b = _time_events(batched, 10)
+    ms_s = _time_events(singles, 5)
+    alg_b = 2592 * v
+    out["point_sources_32c64"] = {
+        "workload": "Q on 12 point-source right-hand sides, 32^3x64, F32 spinors, 18-real F32 links",
+        "batched_ms": round(ms_b, 4), "single_rhs_ms": round(ms_s, 4), "speedup": round(ms_s / ms_b, 3),
+        "alg_bytes_batched": alg_b, "alg_bytes_single": 12 * 480 * v,
+        "batched_hbm_gbs": round(alg_b / (ms_b * 1e-3) / 1e9, 1),
+        "batched_frac_hbm": round(alg_b / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "single_hbm_gbs": round(12 * 480 * v / (ms_s * 1e-3) / 1e9, 1)}
+    log(f"batch leg: 12 point sources batched {ms_b:.3f} ms vs single {ms_s:.3f} ms")
+    del x, y, xs, ys, U
+    torch.cuda.empty_cache()
+
+    sets = []
+    nsites = 0
+    for copy in range(3):
+        jobs = []
+        for k, d in enumerate(MULTI_DIMS):
+            gg = ndq.Geometry(d)
+            if copy == 0:
+                nsites += gg.volume
+            uu = torch.from_numpy(synthetic.gauge_field(d, seed=1001 + k)).to(dev)
+            UU = ndq.GaugeField.pack(gg, uu, ndq.F32, 12)
+            xx = ndq.SpinorField.pack(gg, torch.from_numpy(synthetic.spinor(gg.volume, nrhs=4, seed=1002 + k)).to(dev),
+                                      ndq.F32, ndq.FULL)
+            jobs.append((gg, UU, M, xx, xx.like()))
+        sets.append(jobs)
+    it = {"k": 0}
+
+    def multi():
+        ndq.apply_Q_multi(sets[it["k"] % 3])
+        it["k"] += 1
+
+    def separate():
+        for (gg, UU, m, xx, yy) in sets[it["k"] % 3]:
+            ndq.apply_Q(gg, UU, m, xx, yy)
+        it["k"] += 1
+
+    multi()
+    separate()
+    ms_m = _time_events(multi, 30)
+    ms_sep = _time_events(separate, 30)
+    alg_m = nsites * (4 * 192 + 4 * 48)
+    out["multi_lattice"] = {
+        "workload": "Q on 8^4 + 12^4 + 16^3x32 at 4 RHS each, F32 spinors, 12-real F32 links",
+        "sites": nsites, "persistent_ms": round(ms_m, 4), "separate_ms": round(ms_sep, 4),
+        "speedup": round(ms_sep / ms_m, 3), "alg_bytes": alg_m,
+        "persistent_hbm_gbs": round(alg_m / (ms_m * 1e-3) / 1e9, 1)}
+    log(f"batch leg: multi-lattice persistent {ms_m:.4f} ms vs separate {ms_sep:.4f} ms")
+    return out
+
+
+def graph_leg(log):
+    """Rational sign(Q) (Zolotarev, 12 shifts, no low modes, FP64) applied with
+    each block of 8 multi-shift iterations launched eagerly or replayed from a
+    captured HIP graph; wall time per apply (host synchronised)."""
+    import torch
+    import synthetic
+    import paper_1010_5636_amd as ndq
+    dev = torch.device("cuda")
+    out = {}
+    for d in ((8, 8, 8, 8), (32, 16, 16, 16)):
+        g = ndq.Geometry(d)
+        U = ndq.GaugeField.pack(g, torch.from_numpy(synthetic.gauge_field(d)).to(dev), ndq.F64, 18)
+        x = ndq.SpinorField.pack(g, torch.from_numpy(synthetic.spinor(g.volume)).to(dev), ndq.F64, ndq.FULL)
+        y = x.like()
+        ap = ndq.Approx(ndq.ZOLOTAREV, 0.08, 12)
+        res = {}
+        for graph in (False, True):
+            ov = ndq.Overlap(g, M, ap, LAM_MAX, tol=1e-10, check_every=8, graph=graph)
+            st = ndq.apply_sign(g, U, ov, x, y)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n = 5
+            for _ in range(n):
+                st = ndq.apply_sign(g, U, ov, x, y)
+            torch.cuda.synchronize()
+            res["graph" if graph else "eager"] = {"ms": round((time.perf_counter() - t0) * 1e3 / n, 3),
+                                                  "cg_iterations": st["iterations"]}
+        res["speedup"] = round(res["eager"]["ms"] / res["graph"]["ms"], 3)
+        out["x".join(str(k) for k in d[::-1])] = res
+        log(f"graph leg: {d} eager {res['eager']['ms']} ms, graph {res['graph']['ms']} ms")
+    return out
+
+
+def autograd_leg(log):
+    """S = psi^H Q^2 psi on 16^3 x 32 in FP64 through the torch autograd function
+    (forward Q, backward Q and the su(3) force kernel, canonical tensors in and
+    out), and the force kernel alone (4 links + psi + g read, 4 x 8 reals written
+    per site)."""
+    import torch
+    import synthetic
+    import paper_1010_5636_amd as ndq
+    dev = torch.device("cuda")
+    g = ndq.Geometry(DIMS)
+    v = g.volume
+    links = torch.from_numpy(synthetic.gauge_field(DIMS)).to(dev).requires_grad_(True)
+    psi = torch.from_numpy(synthetic.spinor(v)).to(dev).requires_grad_(True)
+
+    def step():
+        y = ndq.QFunction.apply(psi, links, g, M)
+        s = (y.conj() * y).real.sum()
+        s.backward()
+
+    step()
+    ms_step = _time_events(step, 10)
+    U = ndq.GaugeField.pack(g, links.detach(), ndq.F64, 18)
+    x = ndq.SpinorField.pack(g, psi.detach(), ndq.F64, ndq.FULL)
+    gy = ndq.SpinorField.pack(g, torch.from_numpy(synthetic.spinor(v, seed=4)).to(dev), ndq.F64, ndq.FULL)
+    f = torch.empty((v, 4, 8), dtype=torch.float64, device=dev)
+    from paper_1010_5636_amd.ndq import lib, _ptr, _check
+    import ctypes
+
+    def force_only():
+        _check(lib().ndq_gauge_force(g.handle, ctypes.byref(U.desc), ctypes.byref(x.desc), ctypes.byref(gy.desc),
+                                     _ptr(f), None, None))
+
+    force_only()
+    ms_f = _time_events(force_only, 50)
+    # per site: its 4 links, psi and g once each (the x + mu neighbours are
+    # other sites' own values), 4 x 8 force components written
+    bytes_site = 4 * 144 + 2 * 192 + 4 * 8 * 8
+    out = {"workload": "S = psi^H Q^2 psi, 16^3x32, FP64, 18-real links",
+           "autograd_step_ms": round(ms_step, 4), "force_kernel_us": round(ms_f * 1e3, 2),
+           "force_alg_bytes": bytes_site * v,
+           "force_hbm_gbs": round(bytes_site * v / (ms_f * 1e-3) / 1e9, 1)}
+    log(f"autograd leg: step {ms_step:.3f} ms, force kernel {ms_f * 1e3:.1f} us")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +387,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run a device-to-device copy of BYTES bytes (counter calibration)")
     ap.add_argument("--no-solve", action="store_true", help="skip the 24^3x48 D_N solve leg")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batching, graph and autograd legs")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: multi-GPU runs are not part of this build "
@@ -221,6 +423,11 @@ def main():
             o = e.like(parity=ndq.ODD)
             sets.append((U, e, o))
         torch.cuda.synchronize()
+        if args.no_autotune:
+            tune = None
+        else:
+            tune = ndq.autotune(g, sets[0][0], sp, reps=200, rotate_bytes=int(ROTATE_BYTES))
+        launch = ndq.ndq.get_launch(sp, lp, recon)
 
         def step(k):
             U, e, o = sets[k % nsets]
@@ -277,6 +484,8 @@ def main():
             "kernel_gflops": FLOP_PER_SITE * vh / k_avg / 1e9,
             "frac_hbm": alg_bytes / k_avg / 1e9 / HBM_PEAK_GBS,
             "nsets": nsets,
+            "launch": launch,
+            "autotune_us": None if tune is None else {k: round(t, 3) for k, t in tune["us"].items()},
         }
         del sets, graph
         torch.cuda.synchronize()
@@ -291,7 +500,7 @@ def main():
 
     head = fmts[0][0]
     hr = results[head]
-    traffic = read_traffic(head)
+    traffic = read_traffic(head, hr["launch"])
     out = {
         "metric": "Dslash GFLOP/s + HBM GB/s; D_N solves/s mixed vs FP64 at 1e-10 rel resid",
         "value": hr["gflops"],
@@ -312,13 +521,18 @@ def main():
                    "dims": list(DIMS), "flop_per_site": FLOP_PER_SITE, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(hr["hbm_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(hr["frac_hbm"], 4), "traffic": traffic,
-                     "kernel": "k_wilson (even/odd dslash)", "alg_bytes_per_launch": hr["alg_bytes_per_launch"],
+                     "kernel": kernel_name(hr["launch"]), "alg_bytes_per_launch": hr["alg_bytes_per_launch"],
                      "kernel_us_avg": round(hr["kernel_us_avg"], 3)},
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in r.items()}
                      for k, r in results.items()},
     }
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)  # noqa: E731
     if not args.no_solve:
-        out["dn_solve"] = solve_leg(lambda msg: print(msg, file=sys.stderr, flush=True))
+        out["dn_solve"] = solve_leg(log)
+    if not args.no_extra:
+        out["batching"] = batch_leg(log)
+        out["graph_multishift"] = graph_leg(log)
+        out["autograd"] = autograd_leg(log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

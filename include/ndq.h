@@ -141,8 +141,9 @@ int ndq_apply_Q(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spino
  * computed from them), so its results equal that call's bit for bit (and, for
  * nrhs = 1, those of the one-lane-per-site launch shape, block 64/128/256).
  * All jobs share the spinor precision and the link format; 1 <= njobs <= 8;
- * in, out: NDQ_FULL, same precision and nrhs, not aliased.  The grid fills the
- * device once and walks the joint tile list.  Asynchronous. */
+ * in, out: NDQ_FULL, same precision and nrhs, not aliased.  A fixed grid (four
+ * times the workgroups the device holds at once) walks the joint tile list in
+ * contiguous chunks.  Asynchronous. */
 typedef struct {
     const ndq_geom* g;
     const ndq_gauge* U;
@@ -342,6 +343,9 @@ int ndq_set_launch(int block, int xcd_remap);
 /* The same for one storage format only (spinor precision, link precision,
  * recon); the autotuner records its choice per format this way. */
 int ndq_set_launch_for(int sprec, int lprec, int recon, int block, int xcd_remap);
+
+/* The launch shape currently used for one storage format (host outputs). */
+int ndq_get_launch_for(int sprec, int lprec, int recon, int* block, int* xcd_remap);
 
 /* Autotuner of the launch shape: times `reps` even/odd dslash applies on
  * lattice g with links U and spinors of precision sprec for each launch shape

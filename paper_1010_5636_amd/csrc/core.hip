@@ -196,6 +196,16 @@ extern "C" int ndq_set_launch_for(int sprec, int lprec, int recon, int block, in
     return NDQ_OK;
 }
 
+extern "C" int ndq_get_launch_for(int sprec, int lprec, int recon, int* block, int* xcd_remap) {
+    if (sprec < NDQ_F64 || sprec > NDQ_F16 || lprec < NDQ_F64 || lprec > NDQ_F16 ||
+        (recon != 18 && recon != 12 && recon != 8) || !block || !xcd_remap)
+        return ndq::fail(NDQ_EINVAL, "ndq_get_launch_for: bad format (%d, %d, %d) or NULL output", sprec, lprec, recon);
+    const ndq::Tuning& t = ndq::tuning(sprec, lprec, recon);
+    *block = t.block;
+    *xcd_remap = t.xcd_remap;
+    return NDQ_OK;
+}
+
 extern "C" int ndq_set_launch(int block, int xcd_remap) {
     if (block != 0 && block != 64 && block != 128 && block != 256)
         return ndq::fail(NDQ_EINVAL, "ndq_set_launch: block must be 0, 64, 128 or 256 (got %d)", block);

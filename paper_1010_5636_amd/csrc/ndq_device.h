@@ -172,6 +172,10 @@ template <> struct SpinorIO<P32> {
     __device__ static __forceinline__ void store_comp(const SpinorView& v, int64_t s, int c, C<R> x) {
         reinterpret_cast<float2*>(v.base)[2 * ((int64_t)(c >> 1) * v.stride + s) + (c & 1)] = make_float2(x.r, x.i);
     }
+    // components 2j and 2j+1 (the whole 16-byte word of plane j)
+    __device__ static __forceinline__ void store_plane(const SpinorView& v, int64_t s, int j, C<R> x, C<R> y) {
+        reinterpret_cast<float4*>(v.base)[(int64_t)j * v.stride + s] = make_float4(x.r, x.i, y.r, y.i);
+    }
 };
 
 template <> struct SpinorIO<P16> {
@@ -237,24 +241,38 @@ struct LinkFmt {
     static constexpr int kWords = kBytes / 4;
 };
 
-template <int P, int RECON>
+// NT = true loads with the non-temporal hint.  An even/odd dslash reads every
+// link exactly once, so there the hint keeps links from displacing the spinor
+// words that neighbouring sites re-read from the caches; a full Q apply reads
+// each link twice (as forward link of its site and backward link of the
+// neighbour), and there the second read should find it cached (NT = false).
+typedef unsigned int u32x4_v __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2_v __attribute__((ext_vector_type(2)));
+
+template <bool NT, typename T>
+__device__ __forceinline__ T load_hinted(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <int P, int RECON, bool NT = false>
 __device__ __forceinline__ void link_load_words(const char* base, int32_t vh, int blk, int32_t i, uint32_t w[]) {
     using F = LinkFmt<P, RECON>;
     const char* b = base + (int64_t)blk * F::kBytes * vh;
 #pragma unroll
     for (int j = 0; j < F::kN16; ++j) {
-        const uint4 x = reinterpret_cast<const uint4*>(b + (int64_t)j * 16 * vh)[i];
+        const u32x4_v x = load_hinted<NT>(reinterpret_cast<const u32x4_v*>(b + (int64_t)j * 16 * vh) + i);
         w[4 * j + 0] = x.x;
         w[4 * j + 1] = x.y;
         w[4 * j + 2] = x.z;
         w[4 * j + 3] = x.w;
     }
     if constexpr (F::kTail == 8) {
-        const uint2 x = reinterpret_cast<const uint2*>(b + (int64_t)F::kN16 * 16 * vh)[i];
+        const u32x2_v x = load_hinted<NT>(reinterpret_cast<const u32x2_v*>(b + (int64_t)F::kN16 * 16 * vh) + i);
         w[4 * F::kN16 + 0] = x.x;
         w[4 * F::kN16 + 1] = x.y;
     } else if constexpr (F::kTail == 4) {
-        w[4 * F::kN16] = reinterpret_cast<const uint32_t*>(b + (int64_t)F::kN16 * 16 * vh)[i];
+        w[4 * F::kN16] = load_hinted<NT>(reinterpret_cast<const uint32_t*>(b + (int64_t)F::kN16 * 16 * vh) + i);
     }
 }
 

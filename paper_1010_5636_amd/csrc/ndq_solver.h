@@ -2,6 +2,7 @@
 #pragma once
 
 #include <functional>
+#include <string>
 #include <vector>
 
 #include "ndq_internal.h"
@@ -136,6 +137,8 @@ int q_blocks(const ndq_geom* g, const ndq_gauge* U, int sprec);
 // Records the kernel launches `body` makes on the stream it is given into a HIP
 // graph and launches the graph on `st` (kept instantiated graphs are refreshed
 // with hipGraphExecUpdate).  `body` must launch kernels only.
-int launch_captured(const std::function<int(hipStream_t)>& body, hipStream_t st);
+// `key` (may be empty): bytes that determine every argument of the sequence;
+// an equal key replays the kept graph without capturing.
+int launch_captured(const std::function<int(hipStream_t)>& body, hipStream_t st, const std::string& key);
 
 }  // namespace ndq

@@ -191,6 +191,37 @@ int rational_apply(const ndq_geom* g, const ndq_gauge* U, double m, const Approx
         *qcount += 2;
         ++it;
     }
+    // everything the captured iterations depend on: lattice, links, mass,
+    // launch shape, the workspace (all vectors and device scalars live in it)
+    // and the shift constants
+    std::string key;
+    if (p->graph) {
+        struct {
+            const void* g;
+            int32_t dims[4];      // a freed and re-created geometry may reuse the address
+            const void* links;
+            int32_t prec, lprec, recon, every, block, xcd;
+            double m;
+            const void* r;
+            const void* ws;
+        } head;
+        memset(&head, 0, sizeof(head));
+        const Tuning& tu = tuning(prec, U->prec, U->recon);
+        head.g = g;
+        for (int d = 0; d < 4; ++d) head.dims[d] = g->dims[d];
+        head.links = U->data;
+        head.prec = prec;
+        head.lprec = U->prec;
+        head.recon = U->recon;
+        head.every = every;
+        head.block = tu.block;
+        head.xcd = tu.xcd_remap;
+        head.m = m;
+        head.r = r.data;
+        head.ws = sc.ms;
+        key.assign(reinterpret_cast<const char*>(&head), sizeof(head));
+        key.append(reinterpret_cast<const char*>(&k), sizeof(k));
+    }
     while (!done) {
         if (p->graph) {
             rc = launch_captured([&](hipStream_t s) -> int {
@@ -199,7 +230,7 @@ int rational_apply(const ndq_geom* g, const ndq_gauge* U, double m, const Approx
                     if (e) return e;
                 }
                 return NDQ_OK;
-            }, st);
+            }, st, key);
             if (rc) return rc;
             *qcount += 2 * every;
             it += every;

@@ -23,7 +23,12 @@ struct WilsonArgs {
     int nv;
     double* partials;          // per-block |out|^2 partial sums (nullptr: none)
     int xcd_remap;
+    int order_c;               // tile order chunk (0: tiles in index order), see tile_order()
 };
+
+// Chunk c of the L2-friendly tile order for tiles of `block` sites on lattice g,
+// or 0 when the lattice does not split into whole tiles per x0 slice.
+int tile_order(const GeomK& g, int block);
 
 // One lattice of a persistent multi-lattice launch of Q (NDQ_FULL fields):
 // views per output parity y address right-hand side 0.

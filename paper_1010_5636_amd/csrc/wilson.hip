@@ -124,21 +124,57 @@ __device__ __forceinline__ void hop_bwd(const C<R> s[12], const C<R> u[3][3], C<
     }
 }
 
-template <int SP, int LP, int RECON, int MU>
+template <int SP, int LP, int RECON, int MU, bool NT>
 __device__ __forceinline__ void hop_pair(const WilsonArgs& a, int p, int32_t i, const int32_t nb[8],
                                          const SpinorView& vin, C<typename SpinorIO<SP>::R> acc[12]) {
     using R = typename SpinorIO<SP>::R;
-    C<R> s[12];
-    C<R> u[3][3];
-    SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[MU], s);
-    link_load<LP, RECON>(a.links, a.g.vh, p * 4 + MU, i, u);
-    hop_fwd<MU>(s, u, acc);
-    SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[4 + MU], s);
-    link_load<LP, RECON>(a.links, a.g.vh, (1 - p) * 4 + MU, nb[4 + MU], u);
-    hop_bwd<MU>(s, u, acc);
+    using F = LinkFmt<LP, RECON>;
+    C<R> sf[12], sb[12];
+    uint32_t wf[F::kWords], wb[F::kWords];
+    C<typename LinkReal<LP>::R> u[3][3];
+    if constexpr (SP != P64) {
+        // all loads of both hops first: one memory round trip instead of two
+        // (FP64 keeps the two trips: its registers would halve the occupancy)
+        SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[MU], sf);
+        link_load_words<LP, RECON, NT>(a.links, a.g.vh, p * 4 + MU, i, wf);
+        SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[4 + MU], sb);
+        link_load_words<LP, RECON, NT>(a.links, a.g.vh, (1 - p) * 4 + MU, nb[4 + MU], wb);
+        __builtin_amdgcn_sched_barrier(0);   // keep the arithmetic below every load
+        link_decode<LP, RECON>(wf, u);
+        hop_fwd<MU>(sf, u, acc);
+        link_decode<LP, RECON>(wb, u);
+        hop_bwd<MU>(sb, u, acc);
+    } else {
+        SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[MU], sf);
+        link_load_words<LP, RECON, NT>(a.links, a.g.vh, p * 4 + MU, i, wf);
+        link_decode<LP, RECON>(wf, u);
+        hop_fwd<MU>(sf, u, acc);
+        SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[4 + MU], sb);
+        link_load_words<LP, RECON, NT>(a.links, a.g.vh, (1 - p) * 4 + MU, nb[4 + MU], wb);
+        link_decode<LP, RECON>(wb, u);
+        hop_bwd<MU>(sb, u, acc);
+    }
 }
 
 __device__ __forceinline__ double coef(const Coef& c) { return c.d ? c.f * (*c.d) : c.f; }
+
+// Tile order for cache reuse of the neighbour spinors.  In index order the
+// tiles holding the x0 neighbours of a tile lie a whole x0 slice (S tiles)
+// away, too far back for that slice's spinors to still be in L2.  With chunk c
+// (c divides S) the position p of a launch is mapped to the tile
+//   x0 = (p mod c N0) / c,  j = (p / c N0) c + p mod c,  tile = x0 S + j,
+// i.e. c consecutive tiles of every x0 slice in turn: x0 neighbours are then c
+// positions apart and x1 neighbours (s1 / tile sites apart) mostly inside the
+// same chunk.  A permutation of the tiles: the arithmetic is unchanged.
+__device__ __forceinline__ int32_t order_tile(int32_t p, int32_t nbx, int n0, int c) {
+    if (c <= 0) return p;
+    const int32_t S = nbx / n0;
+    const int32_t cn = c * n0;
+    const int32_t k = p / cn;
+    const int32_t rem = p - k * cn;
+    const int32_t x0 = rem / c;
+    return x0 * S + k * c + (rem - x0 * c);
+}
 
 // Block index remap that gives each of the 8 XCDs (workgroups dispatched
 // round-robin, linear id mod 8) one contiguous range of tiles, so that
@@ -150,14 +186,16 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned lin, unsigned total) {
     return start + (lin >> 3);
 }
 
-template <int SP, int LP, int RECON, int BLOCK>
+template <int SP, int LP, int RECON, int BLOCK, bool NT>
 __global__ void __launch_bounds__(BLOCK) k_wilson(WilsonArgs a) {
     using R = typename SpinorIO<SP>::R;
     __shared__ double red_lds[BLOCK / 64];
     unsigned lin = blockIdx.y * gridDim.x + blockIdx.x;
     if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x * gridDim.y);
     const int y = (int)(lin / gridDim.x);
-    const int32_t i = (int32_t)(lin - (unsigned)y * gridDim.x) * BLOCK + threadIdx.x;
+    const int32_t i =
+        order_tile((int32_t)(lin - (unsigned)y * gridDim.x), (int32_t)gridDim.x, a.g.n0, a.order_c) * BLOCK +
+        threadIdx.x;
     const int p = a.p0 + y;
     double red = 0.0;
     if (i < a.g.vh) {
@@ -168,10 +206,10 @@ __global__ void __launch_bounds__(BLOCK) k_wilson(WilsonArgs a) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
         const SpinorView& vin = a.in[y];
-        hop_pair<SP, LP, RECON, 0>(a, p, i, nb, vin, acc);
-        hop_pair<SP, LP, RECON, 1>(a, p, i, nb, vin, acc);
-        hop_pair<SP, LP, RECON, 2>(a, p, i, nb, vin, acc);
-        hop_pair<SP, LP, RECON, 3>(a, p, i, nb, vin, acc);
+        hop_pair<SP, LP, RECON, 0, NT>(a, p, i, nb, vin, acc);
+        hop_pair<SP, LP, RECON, 1, NT>(a, p, i, nb, vin, acc);
+        hop_pair<SP, LP, RECON, 2, NT>(a, p, i, nb, vin, acc);
+        hop_pair<SP, LP, RECON, 3, NT>(a, p, i, nb, vin, acc);
 
         const R b = (R)a.b_hop;
         if (a.has_self) {
@@ -221,7 +259,7 @@ __global__ void __launch_bounds__(BLOCK) k_wilson(WilsonArgs a) {
 // meet in LDS and are added in a fixed order; wavefront w then finishes spin
 // component w of the 64 outputs.  For F16 outputs wavefront 0 finishes the
 // whole spinor, because the per-site scale needs all 24 reals.
-template <int SP, int LP, int RECON>
+template <int SP, int LP, int RECON, bool NT>
 __global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
     using R = typename SpinorIO<SP>::R;
     __shared__ C<R> part[4][12][64];
@@ -231,7 +269,8 @@ __global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
     const int y = (int)(lin / gridDim.x);
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int32_t i = (int32_t)(lin - (unsigned)y * gridDim.x) * 64 + lane;
+    const int32_t i =
+        order_tile((int32_t)(lin - (unsigned)y * gridDim.x), (int32_t)gridDim.x, a.g.n0, a.order_c) * 64 + lane;
     const int p = a.p0 + y;
     const bool active = i < a.g.vh;
     if (active) {
@@ -243,10 +282,10 @@ __global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
         for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
         const SpinorView& vin = a.in[y];
         switch (w) {
-            case 0: hop_pair<SP, LP, RECON, 0>(a, p, i, nb, vin, acc); break;
-            case 1: hop_pair<SP, LP, RECON, 1>(a, p, i, nb, vin, acc); break;
-            case 2: hop_pair<SP, LP, RECON, 2>(a, p, i, nb, vin, acc); break;
-            default: hop_pair<SP, LP, RECON, 3>(a, p, i, nb, vin, acc); break;
+            case 0: hop_pair<SP, LP, RECON, 0, NT>(a, p, i, nb, vin, acc); break;
+            case 1: hop_pair<SP, LP, RECON, 1, NT>(a, p, i, nb, vin, acc); break;
+            case 2: hop_pair<SP, LP, RECON, 2, NT>(a, p, i, nb, vin, acc); break;
+            default: hop_pair<SP, LP, RECON, 3, NT>(a, p, i, nb, vin, acc); break;
         }
 #pragma unroll
         for (int k = 0; k < 12; ++k) part[w][k][lane] = acc[k];
@@ -294,6 +333,36 @@ __global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
             }
         } else {
             const int64_t so = (int64_t)a.out[y].site0 + i;
+            if constexpr (SP == P32) {
+                // wavefronts 0..2 finish the two 16-byte planes 2w, 2w+1 each
+                // (components 4w..4w+3), so that every store is a full word
+                if (w < 3) {
+                    C<R> t4[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int c = 4 * w + k;
+                        C<R> t = cadd(cadd(part[0][c][lane], part[1][c][lane]),
+                                      cadd(part[2][c][lane], part[3][c][lane]));
+                        if (a.has_self) {
+                            const C<R> sf = SpinorIO<SP>::load_comp(a.self[y], (int64_t)a.self[y].site0 + i, c);
+                            t = {as * sf.r + b * t.r, as * sf.i + b * t.i};
+                        } else {
+                            t = cscale(b, t);
+                        }
+                        if (a.gamma5 && c >= 6) t = cneg(t);
+                        t = cscale(c0, t);
+                        for (int j = 0; j < a.nv; ++j) {
+                            const C<R> vv = SpinorIO<SP>::load_comp(a.v[j][y], (int64_t)a.v[j][y].site0 + i, c);
+                            const R cj = (R)coef(a.cv[j]);
+                            t = {t.r + cj * vv.r, t.i + cj * vv.i};
+                        }
+                        t4[k] = t;
+                        red += (double)t.r * t.r + (double)t.i * t.i;
+                    }
+                    SpinorIO<SP>::store_plane(a.out[y], so, 2 * w, t4[0], t4[1]);
+                    SpinorIO<SP>::store_plane(a.out[y], so, 2 * w + 1, t4[2], t4[3]);
+                }
+            } else {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const int c = 3 * w + k;
@@ -313,6 +382,7 @@ __global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
                 }
                 SpinorIO<SP>::store_comp(a.out[y], so, c, t);
                 red += (double)t.r * t.r + (double)t.i * t.i;
+            }
             }
         }
     }
@@ -336,7 +406,7 @@ __global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
 // views address right-hand side 0; right-hand side r sits r * rhs_bytes
 // further.  `self` may be null (no same-site term).  Must be reached by all
 // 256 threads of the workgroup (it synchronises once).
-template <int SP, int LP, int RECON>
+template <int SP, int LP, int RECON, bool NT>
 __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int p, int32_t tile,
                                           const SpinorView& in, const SpinorView* self, const SpinorView& out,
                                           double a_self, double b_hop, int gamma5, double c0d, int nrhs,
@@ -353,10 +423,10 @@ __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int
         eo_neighbours(g, i, x, nb);
         // wavefront w stages the forward link mu = w and the backward link mu = w
         uint32_t words[F::kWords];
-        link_load_words<LP, RECON>(links, g.vh, p * 4 + w, i, words);
+        link_load_words<LP, RECON, NT>(links, g.vh, p * 4 + w, i, words);
 #pragma unroll
         for (int k = 0; k < F::kWords; ++k) lw[(w * F::kWords + k) * 64 + lane] = words[k];
-        link_load_words<LP, RECON>(links, g.vh, (1 - p) * 4 + w, nb[4 + w], words);
+        link_load_words<LP, RECON, NT>(links, g.vh, (1 - p) * 4 + w, nb[4 + w], words);
 #pragma unroll
         for (int k = 0; k < F::kWords; ++k) lw[((4 + w) * F::kWords + k) * 64 + lane] = words[k];
     }
@@ -373,27 +443,34 @@ __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int
         C<R> acc[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+        // spinor loads of both hops of a direction first (one memory round
+        // trip per direction; FP64: one per hop, for its registers); the
+        // arithmetic order stays fwd 0, bwd 0, fwd 1, ...
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
-            C<R> sp[12];
+            C<R> sf[12], sb[12];
             C<typename LinkReal<LP>::R> u[3][3];
             uint32_t words[F::kWords];
-            SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[mu], sp);
+            SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[mu], sf);
+            if constexpr (SP != P64) {
+                SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[4 + mu], sb);
+                __builtin_amdgcn_sched_barrier(0);
+            }
 #pragma unroll
             for (int k = 0; k < F::kWords; ++k) words[k] = lw[(mu * F::kWords + k) * 64 + lo];
             link_decode<LP, RECON>(words, u);
-            if (mu == 0) hop_fwd<0>(sp, u, acc);
-            if (mu == 1) hop_fwd<1>(sp, u, acc);
-            if (mu == 2) hop_fwd<2>(sp, u, acc);
-            if (mu == 3) hop_fwd<3>(sp, u, acc);
-            SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[4 + mu], sp);
+            if (mu == 0) hop_fwd<0>(sf, u, acc);
+            if (mu == 1) hop_fwd<1>(sf, u, acc);
+            if (mu == 2) hop_fwd<2>(sf, u, acc);
+            if (mu == 3) hop_fwd<3>(sf, u, acc);
+            if constexpr (SP == P64) SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[4 + mu], sb);
 #pragma unroll
             for (int k = 0; k < F::kWords; ++k) words[k] = lw[((4 + mu) * F::kWords + k) * 64 + lo];
             link_decode<LP, RECON>(words, u);
-            if (mu == 0) hop_bwd<0>(sp, u, acc);
-            if (mu == 1) hop_bwd<1>(sp, u, acc);
-            if (mu == 2) hop_bwd<2>(sp, u, acc);
-            if (mu == 3) hop_bwd<3>(sp, u, acc);
+            if (mu == 0) hop_bwd<0>(sb, u, acc);
+            if (mu == 1) hop_bwd<1>(sb, u, acc);
+            if (mu == 2) hop_bwd<2>(sb, u, acc);
+            if (mu == 3) hop_bwd<3>(sb, u, acc);
         }
         const R b = (R)b_hop;
         if (self) {
@@ -421,14 +498,14 @@ __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int
     }
 }
 
-template <int SP, int LP, int RECON>
+template <int SP, int LP, int RECON, bool NT>
 __global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, int nrhs) {
     extern __shared__ uint32_t lw[];   // [8 dirs][link words][64 sites]
     unsigned lin = blockIdx.y * gridDim.x + blockIdx.x;
     if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x * gridDim.y);
     const int y = (int)(lin / gridDim.x);
-    const int32_t tile = (int32_t)(lin - (unsigned)y * gridDim.x);
-    mrhs_tile<SP, LP, RECON>(a.g, a.links, a.p0 + y, tile, a.in[y], a.has_self ? &a.self[y] : nullptr, a.out[y],
+    const int32_t tile = order_tile((int32_t)(lin - (unsigned)y * gridDim.x), (int32_t)gridDim.x, a.g.n0, a.order_c);
+    mrhs_tile<SP, LP, RECON, NT>(a.g, a.links, a.p0 + y, tile, a.in[y], a.has_self ? &a.self[y] : nullptr, a.out[y],
                              a.a_self, a.b_hop, a.gamma5, coef(a.c0), nrhs, lw);
 }
 
@@ -446,21 +523,30 @@ hipError_t allow_lds(K kernel, size_t lds) {
                                (int)lds);
 }
 
-template <int SP, int LP, int RECON>
-hipError_t launch_mrhs_fmt(const WilsonArgs& a, int ny, int nrhs, hipStream_t st) {
+template <int SP, int LP, int RECON, bool NT>
+hipError_t launch_mrhs_nt(const WilsonArgs& a, int ny, int nrhs, hipStream_t st) {
     const dim3 grid((unsigned)((a.g.vh + 63) / 64), ny);
     const size_t lds = mrhs_lds_bytes<SP, LP, RECON>();
-    const hipError_t e = allow_lds(&k_wilson_mrhs<SP, LP, RECON>, lds);
+    const hipError_t e = allow_lds(&k_wilson_mrhs<SP, LP, RECON, NT>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_wilson_mrhs<SP, LP, RECON>), grid, dim3(256), lds, st, a, nrhs);
+    hipLaunchKernelGGL((k_wilson_mrhs<SP, LP, RECON, NT>), grid, dim3(256), lds, st, a, nrhs);
     return hipGetLastError();
+}
+
+// one output parity (ny = 1) reads every link once: non-temporal link loads
+template <int SP, int LP, int RECON>
+hipError_t launch_mrhs_fmt(const WilsonArgs& a, int ny, int nrhs, hipStream_t st) {
+    return ny == 1 ? launch_mrhs_nt<SP, LP, RECON, true>(a, ny, nrhs, st)
+                   : launch_mrhs_nt<SP, LP, RECON, false>(a, ny, nrhs, st);
 }
 
 // Q on several lattices (each with its own links and right-hand sides) in one
 // persistent launch: the tiles of all lattices (both output parities) form one
-// list; a grid that fills the device once walks it, workgroup b taking one
-// contiguous chunk of tiles (chunks adjacent in the list go to workgroups on
-// the same XCD), and each tile runs mrhs_tile with the epilogue of Q.
+// list; a grid of a fixed number of workgroups (a small multiple of what the
+// device holds at once, independent of the lattices) walks it, workgroup b
+// taking one contiguous chunk of tiles (chunks adjacent in the list go to
+// workgroups on the same XCD), and each tile runs mrhs_tile with the epilogue
+// of Q.
 template <int SP, int LP, int RECON>
 __global__ void __launch_bounds__(256) k_wilson_multi(MultiArgs a) {
     extern __shared__ uint32_t lw[];
@@ -475,7 +561,7 @@ __global__ void __launch_bounds__(256) k_wilson_multi(MultiArgs a) {
         const int local = t - J.tile0;
         const int y = local / J.tiles;
         const int32_t tile = local - y * J.tiles;
-        mrhs_tile<SP, LP, RECON>(J.g, J.links, y, tile, J.in[y], &J.self[y], J.out[y], J.a_self, -0.5, 1, 1.0,
+        mrhs_tile<SP, LP, RECON, false>(J.g, J.links, y, tile, J.in[y], &J.self[y], J.out[y], J.a_self, -0.5, 1, 1.0,
                                  J.nrhs, lw);
         __syncthreads();   // the next tile overwrites the staged links
     }
@@ -493,27 +579,37 @@ hipError_t launch_multi_fmt(const MultiArgs& a, hipStream_t st) {
     if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), 256, lds)) !=
         hipSuccess)
         return e;
-    const int grid = std::max(1, std::min(a.total, std::max(1, per_cu) * cus));
+    // four times the workgroups the device holds at once (measured: one
+    // resident set walking long chunks leaves each workgroup a serial chain of
+    // memory round trips; a 4x grid overlaps them and still bounds the grid)
+    const int grid = std::max(1, std::min(a.total, 4 * std::max(1, per_cu) * cus));
     hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(256), lds, st, a);
     return hipGetLastError();
 }
 
-template <int SP, int LP, int RECON>
-hipError_t launch_fmt(const WilsonArgs& a, int ny, int block, hipStream_t st) {
+template <int SP, int LP, int RECON, bool NT>
+hipError_t launch_nt(const WilsonArgs& a, int ny, int block, hipStream_t st) {
     if (block == 0) {
         // direction split: 64 sites per workgroup of 4 wavefronts
         const dim3 grid((unsigned)((a.g.vh + 63) / 64), ny);
-        hipLaunchKernelGGL((k_wilson_dirsplit<SP, LP, RECON>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_wilson_dirsplit<SP, LP, RECON, NT>), grid, dim3(256), 0, st, a);
         return hipGetLastError();
     }
     const unsigned nbx = (unsigned)((a.g.vh + block - 1) / block);
     const dim3 grid(nbx, ny);
     switch (block) {
-        case 64: hipLaunchKernelGGL((k_wilson<SP, LP, RECON, 64>), grid, dim3(64), 0, st, a); break;
-        case 128: hipLaunchKernelGGL((k_wilson<SP, LP, RECON, 128>), grid, dim3(128), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_wilson<SP, LP, RECON, 256>), grid, dim3(256), 0, st, a); break;
+        case 64: hipLaunchKernelGGL((k_wilson<SP, LP, RECON, 64, NT>), grid, dim3(64), 0, st, a); break;
+        case 128: hipLaunchKernelGGL((k_wilson<SP, LP, RECON, 128, NT>), grid, dim3(128), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_wilson<SP, LP, RECON, 256, NT>), grid, dim3(256), 0, st, a); break;
     }
     return hipGetLastError();
+}
+
+// one output parity (ny = 1) reads every link once: non-temporal link loads
+template <int SP, int LP, int RECON>
+hipError_t launch_fmt(const WilsonArgs& a, int ny, int block, hipStream_t st) {
+    return ny == 1 ? launch_nt<SP, LP, RECON, true>(a, ny, block, st)
+                   : launch_nt<SP, LP, RECON, false>(a, ny, block, st);
 }
 
 }  // namespace
@@ -525,7 +621,11 @@ int wilson_blocks(const ndq_geom* g, int block, int ny) {
     return ((g->vh + per - 1) / per) * ny;
 }
 
-hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& a, int ny, int block, hipStream_t st) {
+hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& args, int ny, int block,
+                         hipStream_t st) {
+    // single-right-hand-side kernels keep the index order (measured faster);
+    // a.order_c stays as the caller set it (0 from wilson_args)
+    const WilsonArgs& a = args;
     const int key = sprec * 1000 + lprec * 100 + recon;
     switch (key) {
         case P64 * 1000 + P64 * 100 + 18: return launch_fmt<P64, P64, 18>(a, ny, block, st);
@@ -545,8 +645,10 @@ hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& a, i
     }
 }
 
-hipError_t launch_wilson_mrhs(int sprec, int lprec, int recon, const WilsonArgs& a, int ny, int nrhs,
+hipError_t launch_wilson_mrhs(int sprec, int lprec, int recon, const WilsonArgs& args, int ny, int nrhs,
                               hipStream_t st) {
+    WilsonArgs a = args;
+    a.order_c = tile_order(a.g, 64);
     const int key = sprec * 1000 + lprec * 100 + recon;
     switch (key) {
         case P64 * 1000 + P64 * 100 + 18: return launch_mrhs_fmt<P64, P64, 18>(a, ny, nrhs, st);
@@ -584,6 +686,16 @@ hipError_t launch_wilson_multi(int sprec, int lprec, int recon, const MultiArgs&
         case P16 * 1000 + P16 * 100 + 12: return launch_multi_fmt<P16, P16, 12>(a, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+int tile_order(const GeomK& g, int block) {
+    const int64_t per_slice = g.vh / g.n0;
+    if (g.n0 < 4 || per_slice * g.n0 != g.vh || per_slice % block) return 0;
+    const int64_t S = per_slice / block;
+    const int64_t s1t = (g.s1 + block - 1) / block;   // x1 neighbours, in tiles
+    for (int64_t c = std::max<int64_t>(2, 4 * s1t); c < S; ++c)
+        if (S % c == 0) return (int)c;
+    return 0;
 }
 
 WilsonArgs wilson_args(const ndq_geom* g, const ndq_gauge* U, int sprec) {

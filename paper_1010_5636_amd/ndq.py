@@ -108,6 +108,8 @@ _SIG = {
     "ndq_spinor_pack": (_I, [_P, _P, ctypes.POINTER(_Spinor), _P]),
     "ndq_spinor_unpack": (_I, [_P, ctypes.POINTER(_Spinor), _P, _P]),
     "ndq_apply_Q": (_I, [_P, ctypes.POINTER(_Gauge), _D, ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P]),
+    "ndq_get_launch_for": (_I, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int)]),
     "ndq_autotune": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                           ctypes.POINTER(_TuneResult), _P]),
     "ndq_apply_Q_multi": (_I, [ctypes.POINTER(_QJob), ctypes.c_int32, _P]),
@@ -191,6 +193,14 @@ def autotune(geom: "Geometry", U: "GaugeField", sprec: int, reps: int = 100, rot
                               ctypes.byref(r), _stream(stream)))
     shapes = {f"block{b}_xcd{x}": r.us[2 * i + x] for i, b in enumerate((0, 64, 128, 256)) for x in (0, 1)}
     return {"block": r.block, "xcd_remap": r.xcd_remap, "us_best": r.us_best, "us": shapes, "nsets": r.nsets}
+
+
+def get_launch(sprec: int, lprec: int, recon: int) -> dict:
+    """The launch shape currently used for one storage format."""
+    b = ctypes.c_int()
+    x = ctypes.c_int()
+    _check(lib().ndq_get_launch_for(sprec, lprec, recon, ctypes.byref(b), ctypes.byref(x)))
+    return {"block": b.value, "xcd_remap": x.value}
 
 
 def set_launch_for(sprec: int, lprec: int, recon: int, block: int, xcd_remap: bool = True):

@@ -112,3 +112,32 @@ def test_graph_solve_equals_eager(setup):
         else:
             assert torch.equal(x.buf, out[graph])
     assert torch.equal(out[True], out[False])
+
+
+def test_graph_after_new_geometry():
+    """A kept graph is never replayed for another lattice, even when a new
+    geometry or workspace reuses a freed one's address."""
+    import gc
+    for dims in ((4, 4, 4, 4), (8, 4, 6, 2), (4, 4, 4, 4), (6, 2, 4, 4)):
+        g = ndq.Geometry(dims)
+        v = g.volume
+        u = synthetic.gauge_field(dims)
+        U = ndq.GaugeField.pack(g, cu(u), ndq.F64, 18)
+        psi = synthetic.spinor(v, seed=5)
+        ap = ndq.Approx(ndq.ZOLOTAREV, 0.08, 10)
+        outs = []
+        for graph in (False, True, True):
+            ov = ndq.Overlap(g, M, ap, LMAX, tol=1e-12, check_every=4, graph=graph)
+            x = ndq.SpinorField.pack(g, cu(psi), ndq.F64, ndq.FULL)
+            y = x.like()
+            ndq.apply_sign(g, U, ov, x, y)
+            torch.cuda.synchronize()
+            outs.append(y.buf.clone())
+            del ov, x, y
+        assert torch.equal(outs[1], outs[0]) and torch.equal(outs[2], outs[0]), dims
+        ref = sign.sign_rational(lambda w: dirac.apply_Q(u, w, M, dims), psi, approx.zolotarev(0.08, 10), LMAX,
+                                 tol=1e-13)
+        got = ndq.SpinorField(g, ndq.F64, ndq.FULL, buffer=outs[0]).unpack().cpu().numpy()[0]
+        assert np.linalg.norm(got - ref) <= 1e-9 * np.linalg.norm(psi)
+        del g, U
+        gc.collect()
