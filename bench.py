@@ -389,6 +389,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the 24^3x48 D_N solve leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the batching, graph and autograd legs")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--launch", default="", metavar="BLOCK,XCD",
+                    help="force one launch shape for every format (no autotuning), e.g. 0,1")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: multi-GPU runs are not part of this build "
@@ -423,7 +425,11 @@ def main():
             o = e.like(parity=ndq.ODD)
             sets.append((U, e, o))
         torch.cuda.synchronize()
-        if args.no_autotune:
+        if args.launch:
+            b, x = (int(t) for t in args.launch.split(","))
+            ndq.set_launch_for(sp, lp, recon, b, bool(x))
+            tune = None
+        elif args.no_autotune:
             tune = None
         else:
             tune = ndq.autotune(g, sets[0][0], sp, reps=200, rotate_bytes=int(ROTATE_BYTES))

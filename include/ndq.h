@@ -353,7 +353,7 @@ int ndq_get_launch_for(int sprec, int lprec, int recon, int* block, int* xcd_rem
  * rotating copies of (links, even spinor, odd spinor) so that consecutive
  * applies stream from HBM as in a solver (rotate_bytes <= 0: one set), and
  * records the fastest shape for that storage format as ndq_set_launch_for
- * does.  Allocates and frees its own device buffers; synchronises `stream`.
+ * does; the shape already in use is kept if it is within 3% of the fastest.  Allocates and frees its own device buffers; synchronises `stream`.
  * Errors: NDQ_EINVAL, NDQ_EPREC, NDQ_EHIP (the previous shape is kept). */
 typedef struct {
     int32_t block;        /* chosen shape                                            */

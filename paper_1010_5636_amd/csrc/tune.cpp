@@ -117,6 +117,16 @@ extern "C" int ndq_autotune(const ndq_geom* g, const ndq_gauge* U, int sprec, in
         }
     }
     cleanup();
+    // keep the shape in use unless another is more than 3% faster: shapes
+    // within timing noise of each other should not flip from run to run
+    int cur = 0;
+    for (int b = 0; b < 4; ++b)
+        if (kBlocks[b] == saved.block) cur = 2 * b + saved.xcd_remap;
+    if (out->us[cur] <= 1.03 * best) {
+        best_b = saved.block;
+        best_x = saved.xcd_remap;
+        best = out->us[cur];
+    }
     Tuning& t = tuning(sprec, U->prec, U->recon);
     t.block = best_b;
     t.xcd_remap = best_x;

@@ -1,14 +1,15 @@
 """Summaries of rocprofv3 output for the stencil kernels.
 
     python -m paper_1010_5636_amd.profiling stats   <trace_dir>  <out.txt>
-    python -m paper_1010_5636_amd.profiling traffic <fetch_dir> <write_dir> <copy_bytes> <out.json>
+    python -m paper_1010_5636_amd.profiling traffic <fetch_dir> <write_dir> <copy_bytes> <out.json> <cmd> <block,xcd>
 
 ``stats`` condenses ``*kernel_stats.csv`` (from ``rocprofv3 --kernel-trace
 --stats``) into a short text table.  ``traffic`` reads the per-dispatch
 FETCH_SIZE and WRITE_SIZE counters (KiB, from two ``rocprofv3 --pmc`` runs),
 calibrates them against a plain device-to-device copy of ``copy_bytes`` bytes
 each way recorded in the same runs, and writes the HBM bytes per launch of
-every Wilson stencil instantiation, tagged with the hash of the kernel source.
+every even/odd dslash instantiation, tagged with the hash of the kernel
+source and the launch shape (block, XCD remap) the runs were forced to.
 """
 from __future__ import annotations
 
@@ -21,7 +22,8 @@ import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["paper_1010_5636_amd/csrc/wilson.hip", "paper_1010_5636_amd/csrc/ndq_device.h"]
+KERNEL_SOURCES = ["paper_1010_5636_amd/csrc/wilson.hip", "paper_1010_5636_amd/csrc/wilson.h",
+                  "paper_1010_5636_amd/csrc/ndq_device.h"]
 _FMT = re.compile(r"k_wilson(_dirsplit)?<(\d+), (\d+), (\d+)")
 _PREC = {0: "f64", 1: "f32", 2: "f16"}
 
@@ -94,7 +96,7 @@ def _copy_reading(vals: dict, copy_bytes: int):
     return best
 
 
-def traffic(fetch_dir: str, write_dir: str, copy_bytes: int, command: str):
+def traffic(fetch_dir: str, write_dir: str, copy_bytes: int, command: str, launch=None):
     fetch = counters(fetch_dir, "FETCH_SIZE")
     write = counters(write_dir, "WRITE_SIZE")
     cf = _copy_reading(fetch, copy_bytes)
@@ -117,7 +119,7 @@ def traffic(fetch_dir: str, write_dir: str, copy_bytes: int, command: str):
         rec["formats"].setdefault(fmt, {})
         rec["formats"][fmt].update({"kernel": name[:120], "fetch_bytes_per_launch": fb,
                                     "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
-                                    "dispatches": len(v)})
+                                    "dispatches": len(v), "launch": launch})
     return rec
 
 
@@ -131,7 +133,11 @@ def main(argv):
         return 0
     if len(argv) >= 5 and argv[0] == "traffic":
         cmd = argv[5] if len(argv) > 5 else ""
-        rec = traffic(argv[1], argv[2], int(argv[3]), cmd)
+        launch = None
+        if len(argv) > 6:
+            b, x = (int(t) for t in argv[6].split(","))
+            launch = {"block": b, "xcd_remap": x}
+        rec = traffic(argv[1], argv[2], int(argv[3]), cmd, launch)
         with open(argv[4], "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec, indent=1))
