@@ -198,6 +198,29 @@ def _time_events(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def copy_reference(nbytes, reps=400):
+    """A plain device-to-device copy (torch) moving the same number of HBM bytes
+    as one headline dslash (half read, half written), on rotating buffers:
+    what a kernel with no arithmetic and no gathers achieves at this size."""
+    import torch
+    half = int(nbytes) // 2
+    nsets = max(2, int(np.ceil(ROTATE_BYTES / (2 * half))))
+    src = [torch.ones(half, dtype=torch.uint8, device="cuda") for _ in range(nsets)]
+    dst = [torch.empty(half, dtype=torch.uint8, device="cuda") for _ in range(nsets)]
+    it = {"k": 0}
+
+    def one():
+        k = it["k"] % nsets
+        dst[k].copy_(src[k])
+        it["k"] += 1
+
+    for _ in range(2 * nsets):
+        one()
+    ms = _time_events(one, reps)
+    return {"bytes": 2 * half, "us": round(ms * 1e3, 3), "gbs": round(2 * half / (ms * 1e-3) / 1e9, 1),
+            "frac": round(2 * half / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 BATCH_DIMS = (64, 32, 32, 32)
 MULTI_DIMS = [(8, 8, 8, 8), (12, 12, 12, 12), (32, 16, 16, 16)]
 
@@ -528,7 +551,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(hr["hbm_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(hr["frac_hbm"], 4), "traffic": traffic,
                      "kernel": kernel_name(hr["launch"]), "alg_bytes_per_launch": hr["alg_bytes_per_launch"],
-                     "kernel_us_avg": round(hr["kernel_us_avg"], 3)},
+                     "kernel_us_avg": round(hr["kernel_us_avg"], 3),
+                     "copy_same_bytes": copy_reference(hr["alg_bytes_per_launch"])},
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in r.items()}
                      for k, r in results.items()},
     }

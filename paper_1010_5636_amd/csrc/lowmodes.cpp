@@ -42,6 +42,7 @@ struct LmCtx {
     hipStream_t st;
     int64_t vb;              // bytes per FP64 full spinor
     char *VA, *VB, *W, *QU, *UU;
+    char* SB = nullptr;      // block of nkeep vectors: Q T_k of the block filter
     ndq_spinor X0, X1, S;
     double *partials, *dots, *Ydev, *coef, *scal;
     int64_t qcount = 0;
@@ -52,6 +53,13 @@ struct LmCtx {
                const Coef* cv = nullptr) {
         qcount += 1;
         return q_combo(g, U, m, in, out, Coef{c0, nullptr}, nv, v, cv, nullptr, st);
+    }
+    ndq_spinor block(char* base, int nb) const { return ndq_spinor{base, NDQ_F64, NDQ_FULL, nb}; }
+    // the same as qapply for the nb vectors of a block, in one multi-RHS launch
+    int qapply_block(const ndq_spinor* in, const ndq_spinor* out, double c0, int nv = 0,
+                     const ndq_spinor* const* v = nullptr, const Coef* cv = nullptr) {
+        qcount += in->nrhs;
+        return q_combo_block(g, U, m, in, out, Coef{c0, nullptr}, nv, v, cv, st);
     }
     int copy(const ndq_spinor* dst, const ndq_spinor* src, double c = 1.0) {
         const ndq_spinor* v[1] = {src};
@@ -113,6 +121,33 @@ int apply_filter(LmCtx& c, const ndq_spinor* v, const ndq_spinor* out, double a,
     return c.copy(out, tc);
 }
 
+// Y = T_d(A~) X for all nb vectors of the block X at once (the recurrence of
+// apply_filter with multi-RHS stencil launches: the links are read once per
+// step for the whole block).  T_{k+1} overwrites T_{k-1}, so the iterates
+// alternate between X and Y; X is overwritten.  Needs c.SB (nb vectors).
+int apply_filter_block(LmCtx& c, char* X, char* Y, int nb, double a, double b, int d) {
+    const double c1 = 2.0 / (b - a), c2 = -(a + b) / (b - a);
+    int rc;
+    const ndq_spinor s = c.block(c.SB, nb);
+    ndq_spinor tp = c.block(X, nb);   // T_{k-1}
+    ndq_spinor tc = c.block(Y, nb);   // T_k
+    if ((rc = c.qapply_block(&tp, &s, 1.0))) return rc;
+    {
+        const ndq_spinor* vv[1] = {&tp};
+        const Coef cv[1] = {Coef{c2, nullptr}};
+        if ((rc = c.qapply_block(&s, &tc, c1, 1, vv, cv))) return rc;
+    }
+    for (int k = 2; k <= d; ++k) {
+        if ((rc = c.qapply_block(&tc, &s, 1.0))) return rc;
+        const ndq_spinor* vv[2] = {&tc, &tp};
+        const Coef cv[2] = {Coef{2.0 * c2, nullptr}, Coef{-1.0, nullptr}};
+        if ((rc = c.qapply_block(&s, &tp, 2.0 * c1, 2, vv, cv))) return rc;   // T_{k+1} into T_{k-1}'s buffer
+        std::swap(tp, tc);
+    }
+    if (tc.data != Y) NDQ_HIP(hipMemcpyAsync(Y, tc.data, (size_t)c.vb * nb, hipMemcpyDeviceToDevice, c.st));
+    return NDQ_OK;
+}
+
 // Lanczos steps j = j0 .. m-1 on the basis block `base` (m+1 vectors), recording
 // the projected matrix T (column j: <V_i, B V_j> for i <= j+1).  op: 0 = A, 1 = filter.
 int lanczos_steps(LmCtx& c, char* base, int j0, int m, std::vector<cd>& T, int op, double a, double b, int d) {
@@ -168,9 +203,9 @@ int rayleigh_ritz_q(LmCtx& c, char*& X, char*& W, char*& XS, char*& WS, int nb, 
                     RRResult& out) {
     const ndq_geom* g = c.g;
     int rc;
-    for (int i = 0; i < nb; ++i) {
-        const ndq_spinor xi = c.vec(X, i), wi = c.vec(W, i);
-        if ((rc = c.qapply(&xi, &wi, 1.0))) return rc;
+    {
+        const ndq_spinor xb = c.block(X, nb), wb = c.block(W, nb);
+        if ((rc = c.qapply_block(&xb, &wb, 1.0))) return rc;
     }
     std::vector<cd> M((size_t)nb * nb), G((size_t)nb * nb), col;
     for (int i = 0; i < nb; ++i) {
@@ -309,6 +344,7 @@ size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params*
     ar.take(vb * nkeep);            // WS
     ar.take(vb * (p->nev + 1));     // QU
     ar.take(vb * (p->nev + 1));     // UU
+    if (p->method != NDQ_LM_LANCZOS) ar.take(vb * nkeep);   // SB
     for (int i = 0; i < 3; ++i) ar.take(vb);
     ar.take(partials_capacity(g, 2 * NDQ_MAX_MODES));
     ar.take(2 * NDQ_MAX_MODES * sizeof(double));
@@ -348,6 +384,7 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     char* WS = static_cast<char*>(ar.take(c.vb * nkeep));
     c.QU = static_cast<char*>(ar.take(c.vb * (nev + 1)));
     c.UU = static_cast<char*>(ar.take(c.vb * (nev + 1)));
+    if (!lanczos) c.SB = static_cast<char*>(ar.take(c.vb * nkeep));
     c.X0 = ws_spinor(ar, g, NDQ_F64);
     c.X1 = ws_spinor(ar, g, NDQ_F64);
     c.S = ws_spinor(ar, g, NDQ_F64);
@@ -398,10 +435,7 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
         const bool fixed_d = d > 0;
         if (!fixed_d) d = filter_degree(a, b, 0.5 * a);
         for (;;) {
-            for (int i = 0; i < nkeep; ++i) {
-                const ndq_spinor xi = c.vec(X, i), yi = c.vec(XS, i);
-                if ((rc = apply_filter(c, &xi, &yi, a, b, d))) return rc;
-            }
+            if ((rc = apply_filter_block(c, X, XS, nkeep, a, b, d))) return rc;
             std::swap(X, XS);
             if ((rc = orthonormalise(c, X, nkeep))) return rc;
             if ((rc = rayleigh_ritz_q(c, X, W, XS, WS, nkeep, nsel, true, rr))) return rc;

@@ -133,6 +133,10 @@ int apply_sign(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* 
 int q_combo(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in, const ndq_spinor* out,
             Coef c0, int nv, const ndq_spinor* const* v, const Coef* cv, double* partials, hipStream_t st);
 int q_blocks(const ndq_geom* g, const ndq_gauge* U, int sprec);
+// The same for in->nrhs right-hand sides in one multi-RHS launch (links staged
+// once per tile); in, out and v share nrhs; no partial sums.
+int q_combo_block(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in, const ndq_spinor* out,
+                  Coef c0, int nv, const ndq_spinor* const* v, const Coef* cv, hipStream_t st);
 
 // Records the kernel launches `body` makes on the stream it is given into a HIP
 // graph and launches the graph on `st` (kept instantiated graphs are refreshed

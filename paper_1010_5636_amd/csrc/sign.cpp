@@ -21,6 +21,27 @@
 
 namespace ndq {
 
+int q_combo_block(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in, const ndq_spinor* out,
+                  Coef c0, int nv, const ndq_spinor* const* v, const Coef* cv, hipStream_t st) {
+    WilsonArgs a = wilson_args(g, U, in->prec);
+    a.p0 = 0;
+    for (int p = 0; p < 2; ++p) {
+        a.in[p] = view_of(g, in, 1 - p, 0);
+        a.self[p] = view_of(g, in, p, 0);
+        a.out[p] = view_of(g, out, p, 0);
+        for (int j = 0; j < nv; ++j) a.v[j][p] = view_of(g, v[j], p, 0);
+    }
+    a.has_self = 1;
+    a.a_self = 4.0 + m;
+    a.b_hop = -0.5;
+    a.gamma5 = 1;
+    a.c0 = c0;
+    a.nv = nv;
+    for (int j = 0; j < nv; ++j) a.cv[j] = cv[j];
+    NDQ_HIP(launch_wilson_mrhs(in->prec, U->prec, U->recon, a, 2, in->nrhs, st));
+    return NDQ_OK;
+}
+
 int q_blocks(const ndq_geom* g, const ndq_gauge* U, int sprec) {
     return wilson_blocks(g, tuning(sprec, U->prec, U->recon).block, 2);
 }

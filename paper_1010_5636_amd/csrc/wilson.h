@@ -64,8 +64,8 @@ inline int recon_index(int recon) { return recon == 18 ? 0 : recon == 12 ? 1 : 2
 WilsonArgs wilson_args(const ndq_geom* g, const ndq_gauge* U, int sprec);
 int wilson_blocks(const ndq_geom* g, int block, int ny);
 hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& a, int ny, int block, hipStream_t st);
-// nrhs right-hand sides (a.in/out/self views point at rhs 0; rhs r at + r * rhs_bytes),
-// links staged once in LDS; epilogue without extra vectors or partial sums.
+// nrhs right-hand sides (a.in/out/self/v views point at rhs 0; rhs r at + r * rhs_bytes),
+// links staged once in LDS; epilogue with up to 3 extra vectors, no partial sums.
 hipError_t launch_wilson_multi(int sprec, int lprec, int recon, const MultiArgs& a, hipStream_t st);
 hipError_t launch_wilson_mrhs(int sprec, int lprec, int recon, const WilsonArgs& a, int ny, int nrhs, hipStream_t st);
 

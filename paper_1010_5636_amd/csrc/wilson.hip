@@ -410,7 +410,8 @@ template <int SP, int LP, int RECON, bool NT>
 __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int p, int32_t tile,
                                           const SpinorView& in, const SpinorView* self, const SpinorView& out,
                                           double a_self, double b_hop, int gamma5, double c0d, int nrhs,
-                                          uint32_t* lw) {
+                                          uint32_t* lw, int nv = 0, const SpinorView* v = nullptr,
+                                          const double* cvd = nullptr) {
     using R = typename SpinorIO<SP>::R;
     using F = LinkFmt<LP, RECON>;
     const int lane = threadIdx.x & 63;
@@ -492,6 +493,15 @@ __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int
         const R c0 = (R)c0d;
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = cscale(c0, acc[k]);
+        for (int j = 0; j < nv; ++j) {
+            SpinorView vj = v[j];
+            vj.base += (int64_t)r * vj.rhs_bytes;
+            C<R> vv[12];
+            SpinorIO<SP>::load(vj, (int64_t)vj.site0 + i, vv);
+            const R cj = (R)cvd[j];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = {acc[k].r + cj * vv[k].r, acc[k].i + cj * vv[k].i};
+        }
         SpinorView vo = out;
         vo.base += (int64_t)r * vo.rhs_bytes;
         SpinorIO<SP>::store(vo, (int64_t)vo.site0 + i, acc);
@@ -505,8 +515,14 @@ __global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, int nrhs) {
     if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x * gridDim.y);
     const int y = (int)(lin / gridDim.x);
     const int32_t tile = order_tile((int32_t)(lin - (unsigned)y * gridDim.x), (int32_t)gridDim.x, a.g.n0, a.order_c);
+    SpinorView vv[3];
+    double cv[3];
+    for (int j = 0; j < a.nv; ++j) {
+        vv[j] = a.v[j][y];
+        cv[j] = coef(a.cv[j]);
+    }
     mrhs_tile<SP, LP, RECON, NT>(a.g, a.links, a.p0 + y, tile, a.in[y], a.has_self ? &a.self[y] : nullptr, a.out[y],
-                             a.a_self, a.b_hop, a.gamma5, coef(a.c0), nrhs, lw);
+                                 a.a_self, a.b_hop, a.gamma5, coef(a.c0), nrhs, lw, a.nv, vv, cv);
 }
 
 template <int SP, int LP, int RECON>
