@@ -76,11 +76,14 @@ struct ForceArgs {
     double2* grad;       // [V][4][3][3] complex (lexicographic) or nullptr
 };
 
+// One workgroup per 64 sites of one parity; wavefront w takes direction mu = w,
+// so the four directions of a site read psi(x) and g(x) from the same cache
+// lines at about the same time.
 template <int RECON>
 __global__ void __launch_bounds__(256) k_force(ForceArgs a) {
-    const int p = blockIdx.y >> 2;
-    const int mu = blockIdx.y & 3;
-    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    const int p = blockIdx.y;
+    const int mu = threadIdx.x >> 6;
+    const int32_t i = blockIdx.x * 64 + (threadIdx.x & 63);
     if (i >= a.g.vh) return;
     const SiteCoord x = eo_coords(a.g, p, i);
     int32_t nb[8];
@@ -180,7 +183,7 @@ extern "C" int ndq_gauge_force(const ndq_geom* g, const ndq_gauge* U, const ndq_
     }
     a.force = d_force;
     a.grad = static_cast<double2*>(d_grad);
-    const dim3 grid((g->vh + 255) / 256, 8);
+    const dim3 grid((g->vh + 63) / 64, 2);
     hipStream_t st = as_stream(stream);
     switch (U->recon) {
         case 18: hipLaunchKernelGGL(k_force<18>, grid, dim3(256), 0, st, a); break;
