@@ -527,6 +527,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # the shapes tuned on the dslash stay out of the legs below (their full-Q
+    # applies run with the default shape)
+    ndq.set_launch(0, True)
     head = fmts[0][0]
     hr = results[head]
     traffic = read_traffic(head, hr["launch"])
