@@ -101,9 +101,27 @@ def test_autotune_keeps_parity(fmt):
         assert res["block"] in (0, 64, 128, 256) and res["xcd_remap"] in (0, 1)
         assert res["nsets"] > 1
         assert all(t > 0 for t in res["us"].values())
-        assert res["us_best"] == min(res["us"].values())
+        # the fastest shape, or the one in use when it is within 3% of the fastest
+        assert res["us_best"] <= 1.03 * min(res["us"].values())
+        assert res["us_best"] == res["us"][f"block{res['block']}_xcd{res['xcd_remap']}"]
+        assert ndq.ndq.get_launch(sp, lp, recon) == {"block": res["block"], "xcd_remap": res["xcd_remap"]}
         ndq.apply_Q(L["g"], L["U"], M, L["x"], L["y"])
         got = L["y"].unpack().cpu().numpy()[0]
         assert rel_l2(got, dirac.apply_Q(L["u"], L["psi"][0], M, dims)) <= TOL[sp]
     finally:
         ndq.set_launch(0, 1)
+
+
+def test_multi_max_jobs():
+    """8 lattices (the maximum) in one launch; 9 are rejected."""
+    specs = [((4, 4, 4, 4), 2), ((2, 2, 2, 2), 1), ((8, 4, 6, 2), 3), ((6, 10, 4, 6), 1), ((4, 2, 2, 2), 5),
+             ((2, 6, 2, 10), 2), ((8, 8, 8, 8), 4), ((4, 4, 2, 6), 1)]
+    lats = [lattice(d, n, 60 + k, ndq.F32, ndq.F32, 18) for k, (d, n) in enumerate(specs)]
+    ndq.apply_Q_multi([(L["g"], L["U"], L["m"], L["x"], L["y"]) for L in lats])
+    for L in lats:
+        got = L["y"].unpack().cpu().numpy()
+        for r in range(L["psi"].shape[0]):
+            assert rel_l2(got[r], dirac.apply_Q(L["u"], L["psi"][r], L["m"], L["dims"])) <= TOL[ndq.F32]
+    extra = lattice((4, 4, 4, 4), 1, 70, ndq.F32, ndq.F32, 18)
+    with pytest.raises(ndq.NdqError):
+        ndq.apply_Q_multi([(L["g"], L["U"], L["m"], L["x"], L["y"]) for L in lats + [extra]])

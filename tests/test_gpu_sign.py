@@ -179,3 +179,22 @@ def test_sign_errors(dense, gpu):
     with pytest.raises(ndq.NdqError) as e:
         ndq.apply_sign(g, gpu["U64"], ov, x, y)
     assert e.value.status == -5
+
+
+def test_sign_max_modes_and_shifts(dense, gpu):
+    """The documented maxima: 64 exactly treated modes and a 32-pole Zolotarev
+    approximant, against the spectral closed form."""
+    nev = 64
+    k = k_low(dense, nev)
+    ap, ref_ap = ndq.Approx(ndq.ZOLOTAREV, k, 32), approx.zolotarev(k, 32)
+    got, st = run_sign(gpu, dense, ap, nev=nev)
+    ref = sign.dense_sign_approx(dense["q"], ref_ap, LMAX, n_low=nev, eig=dense["eig"]) @ dense["psi"].ravel()
+    assert rel(got, ref) <= 1e-9, (rel(got, ref), st)
+    with pytest.raises(ndq.NdqError):
+        ndq.Approx(ndq.ZOLOTAREV, k, 33)
+    nu, m = lowmodes.dense_lowmodes(dense["q"], 65, eig=dense["eig"])
+    modes = ndq.SpinorField.pack(gpu["g"], cu(m.reshape(65, 256, 4, 3)), ndq.F64, ndq.FULL)
+    ov = ndq.Overlap(gpu["g"], M, ap, LMAX, modes=modes, nu=nu)
+    x = ndq.SpinorField.pack(gpu["g"], cu(dense["psi"]), ndq.F64, ndq.FULL)
+    with pytest.raises(ndq.NdqError):
+        ndq.apply_sign(gpu["g"], gpu["U64"], ov, x, x.like())
