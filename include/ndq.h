@@ -365,6 +365,17 @@ typedef struct {
 int ndq_autotune(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, int64_t rotate_bytes,
                  ndq_tune_result* out, void* stream);
 
+/* Gram matrix of two blocks of fields, G[i][j] = <A_i, B_j> = sum over sites and
+ * spin-colour components of conj(A_i) B_j (the inner products of the
+ * Rayleigh-Ritz step of Sec. 2.3), computed on the FP64 matrix cores.
+ *   A, B: F64 NDQ_FULL spinors with nrhs = na, nb in [1, 64] (a block is nrhs
+ *   consecutive fields);  d_G: device, na x nb complex doubles (re, im), row-major;
+ *   ws: device workspace of ndq_gram_workspace_bytes(g, na, nb) bytes.
+ * Asynchronous.  Errors: NDQ_EINVAL, NDQ_EPREC, NDQ_ENOMEM. */
+size_t ndq_gram_workspace_bytes(const ndq_geom* g, int na, int nb);
+int ndq_spinor_gram(const ndq_geom* g, const ndq_spinor* A, const ndq_spinor* B, void* d_G, void* ws,
+                    size_t ws_bytes, void* stream);
+
 /* ---- diagnostics -------------------------------------------------------- */
 const char* ndq_last_error(void);
 const char* ndq_status_string(int status);

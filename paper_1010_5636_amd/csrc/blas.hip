@@ -435,6 +435,93 @@ __global__ void __launch_bounds__(kBlock) k_phase_copy(SpinorView src, SpinorVie
     SpinorIO<P64>::store(dst, s, x);
 }
 
+// ---------------------------------------------------------------------------
+// Gram matrix of two blocks of FP64 full spinor fields on the matrix cores:
+//   G[i][j] = <A_i, B_j> = sum over sites and the 12 components of conj(A_i) B_j,
+// a tall-skinny product (K = 12 V, at most 64 x 64 outputs).  One wavefront
+// accumulates a 16-row tile of G against up to four 16-column tiles over a
+// contiguous range of sites with v_mfma_f64_16x16x4f64: lane l supplies
+// A_{16 ti + l%16} and B_{16 tj + l%16} at site s + l/16, so each instruction
+// adds four sites' products; real and imaginary parts take four real products
+// (ar br + ai bi, ar bi - ai br).  The accumulator lane l, element r holds
+// row 4r + l/16, column l%16.  Per-wavefront partial tiles are summed in a
+// fixed order by k_gram_reduce.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_gram(const char* __restrict__ A, int na, const char* __restrict__ B, int nb,
+                                              int64_t vb, int32_t V, int32_t sites_per_wave, int nwaves,
+                                              double* __restrict__ partials) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= nwaves) return;   // whole wavefronts only
+    const int ti = blockIdx.y;
+    const int t = lane & 15, kk = lane >> 4;
+    const int ntj = (nb + 15) / 16;
+    const int NI = 16 * ((na + 15) / 16), NJ = 16 * ntj;
+    const int32_t s0 = (int32_t)((int64_t)wave * sites_per_wave);
+    const int32_t s1 = (int32_t)min((int64_t)V, (int64_t)s0 + sites_per_wave);
+    const int ia = ti * 16 + t;
+    const bool va = ia < na;
+    const char* pa = A + (int64_t)(va ? ia : 0) * vb;
+    v4d re[4], im[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        re[q] = v4d{0.0, 0.0, 0.0, 0.0};
+        im[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    for (int c = 0; c < 12; ++c) {
+        const int64_t plane = (int64_t)c * V;
+        for (int32_t s = s0; s < s1; s += 4) {
+            const int32_t site = s + kk;
+            const bool vs = site < s1;
+            double2 a = make_double2(0.0, 0.0);
+            if (va && vs) a = reinterpret_cast<const double2*>(pa)[plane + site];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q < ntj) {
+                    const int jb = q * 16 + t;
+                    double2 b = make_double2(0.0, 0.0);
+                    if (jb < nb && vs) b = reinterpret_cast<const double2*>(B + (int64_t)jb * vb)[plane + site];
+                    re[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re[q], 0, 0, 0);
+                    re[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, re[q], 0, 0, 0);
+                    im[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im[q], 0, 0, 0);
+                    im[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.x, im[q], 0, 0, 0);
+                }
+            }
+        }
+    }
+    double2* out = reinterpret_cast<double2*>(partials) + (int64_t)wave * NI * NJ;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q < ntj) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = ti * 16 + 4 * r + kk;
+                const int j = q * 16 + t;
+                out[(int64_t)i * NJ + j] = make_double2(re[q][r], im[q][r]);
+            }
+        }
+    }
+}
+
+// G[i][j] = sum over wavefronts w (in order) of the partial tiles.
+__global__ void __launch_bounds__(kBlock) k_gram_reduce(const double* __restrict__ partials, int na, int nb,
+                                                        int nwaves, double* __restrict__ G) {
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= na * nb) return;
+    const int i = e / nb, j = e - (e / nb) * nb;
+    const int NI = 16 * ((na + 15) / 16), NJ = 16 * ((nb + 15) / 16);
+    const double2* p = reinterpret_cast<const double2*>(partials);
+    double sr = 0.0, si = 0.0;
+    for (int w = 0; w < nwaves; ++w) {
+        const double2 v = p[((int64_t)w * NI + i) * NJ + j];
+        sr += v.x;
+        si += v.y;
+    }
+    G[2 * e] = sr;
+    G[2 * e + 1] = si;
+}
+
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -508,6 +595,35 @@ int convert(const ndq_geom* g, const ndq_spinor* dst, const ndq_spinor* src, hip
         case NDQ_F16 * 3 + NDQ_F32: hipLaunchKernelGGL((k_convert<P16, P32>), grid, dim3(kBlock), 0, st, d, s, n); break;
         default: hipLaunchKernelGGL((k_convert<P16, P16>), grid, dim3(kBlock), 0, st, d, s, n); break;
     }
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+namespace {
+constexpr int kGramWaves = 1024;
+int gram_waves(const ndq_geom* g) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kGramWaves, (g->volume + 63) / 64));
+}
+}  // namespace
+
+size_t gram_partials_bytes(const ndq_geom* g, int na, int nb) {
+    const int NI = 16 * ((na + 15) / 16), NJ = 16 * ((nb + 15) / 16);
+    return (size_t)gram_waves(g) * NI * NJ * 2 * sizeof(double);
+}
+
+int gram(const ndq_geom* g, const void* A, int na, const void* B, int nb, double* partials, double* G,
+         hipStream_t st) {
+    if (na < 1 || nb < 1 || na > 64 || nb > 64) return fail(NDQ_EINVAL, "gram: block sizes must be in [1, 64]");
+    const int nw = gram_waves(g);
+    const int64_t V = g->volume;
+    int32_t spw = (int32_t)((V + nw - 1) / nw);
+    spw = (spw + 3) & ~3;
+    const int64_t vb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
+    const dim3 grid((unsigned)((nw + 3) / 4), (unsigned)((na + 15) / 16));
+    hipLaunchKernelGGL(k_gram, grid, dim3(256), 0, st, static_cast<const char*>(A), na, static_cast<const char*>(B),
+                       nb, vb, (int32_t)V, spw, nw, partials);
+    NDQ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks((int64_t)na * nb)), dim3(kBlock), 0, st, partials, na, nb, nw, G);
     NDQ_HIP(hipGetLastError());
     return NDQ_OK;
 }
@@ -615,3 +731,23 @@ int ms_update(const ndq_geom* g, int prec, MsState* s, const MsConst& k, const n
 }
 
 }  // namespace ndq
+
+extern "C" size_t ndq_gram_workspace_bytes(const ndq_geom* g, int na, int nb) {
+    if (!g || na < 1 || nb < 1 || na > 64 || nb > 64) return 0;
+    return ndq::gram_partials_bytes(g, na, nb);
+}
+
+extern "C" int ndq_spinor_gram(const ndq_geom* g, const ndq_spinor* A, const ndq_spinor* B, void* d_G, void* ws,
+                               size_t ws_bytes, void* stream) {
+    using namespace ndq;
+    if (!g || !d_G) return fail(NDQ_EINVAL, "ndq_spinor_gram: NULL argument");
+    int rc = check_spinor(g, A, NDQ_FULL, "ndq_spinor_gram A");
+    if (!rc) rc = check_spinor(g, B, NDQ_FULL, "ndq_spinor_gram B");
+    if (rc) return rc;
+    if (A->prec != NDQ_F64 || B->prec != NDQ_F64) return fail(NDQ_EPREC, "ndq_spinor_gram: F64 fields");
+    if (A->nrhs > 64 || B->nrhs > 64) return fail(NDQ_EINVAL, "ndq_spinor_gram: at most 64 fields per block");
+    const size_t need = gram_partials_bytes(g, A->nrhs, B->nrhs);
+    if (!ws || ws_bytes < need) return fail(NDQ_ENOMEM, "ndq_spinor_gram: workspace too small (need %zu bytes)", need);
+    return gram(g, A->data, A->nrhs, B->data, B->nrhs, static_cast<double*>(ws), static_cast<double*>(d_G),
+                as_stream(stream));
+}

@@ -43,6 +43,8 @@ struct LmCtx {
     int64_t vb;              // bytes per FP64 full spinor
     char *VA, *VB, *W, *QU, *UU;
     char* SB = nullptr;      // block of nkeep vectors: Q T_k of the block filter
+    double* gpart = nullptr; // Gram partial tiles (matrix-core kernel)
+    double* gout = nullptr;  // Gram matrix, device, up to 64 x 64 complex
     ndq_spinor X0, X1, S;
     double *partials, *dots, *Ydev, *coef, *scal;
     int64_t qcount = 0;
@@ -207,14 +209,14 @@ int rayleigh_ritz_q(LmCtx& c, char*& X, char*& W, char*& XS, char*& WS, int nb, 
         const ndq_spinor xb = c.block(X, nb), wb = c.block(W, nb);
         if ((rc = c.qapply_block(&xb, &wb, 1.0))) return rc;
     }
-    std::vector<cd> M((size_t)nb * nb), G((size_t)nb * nb), col;
-    for (int i = 0; i < nb; ++i) {
-        const ndq_spinor wi = c.vec(W, i);
-        if ((rc = c.dots_to_host(X, nb, &wi, col))) return rc;
-        for (int k = 0; k < nb; ++k) M[(size_t)k * nb + i] = col[k];
-        if ((rc = c.dots_to_host(W, nb, &wi, col))) return rc;
-        for (int k = 0; k < nb; ++k) G[(size_t)k * nb + i] = col[k];
-    }
+    // M = X^H W and G = W^H W, one pass over the blocks each (matrix cores)
+    std::vector<cd> M((size_t)nb * nb), G((size_t)nb * nb);
+    if ((rc = gram(g, X, nb, W, nb, c.gpart, c.gout, c.st))) return rc;
+    NDQ_HIP(hipMemcpyAsync(M.data(), c.gout, sizeof(cd) * M.size(), hipMemcpyDeviceToHost, c.st));
+    NDQ_HIP(hipStreamSynchronize(c.st));
+    if ((rc = gram(g, W, nb, W, nb, c.gpart, c.gout, c.st))) return rc;
+    NDQ_HIP(hipMemcpyAsync(G.data(), c.gout, sizeof(cd) * G.size(), hipMemcpyDeviceToHost, c.st));
+    NDQ_HIP(hipStreamSynchronize(c.st));
     for (int i = 0; i < nb; ++i) {
         M[(size_t)i * nb + i] = M[(size_t)i * nb + i].real();
         for (int k = i + 1; k < nb; ++k) {
@@ -351,6 +353,8 @@ size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params*
     ar.take((size_t)2 * (m + 1) * (m + 1) * sizeof(double));
     ar.take(2 * NDQ_MAX_MODES * sizeof(double));
     ar.take(64 * sizeof(double));
+    ar.take(gram_partials_bytes(g, nkeep, nkeep));
+    ar.take(2 * 64 * 64 * sizeof(double));
     return ar.used + 256;
 }
 
@@ -393,6 +397,8 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     c.Ydev = static_cast<double*>(ar.take((size_t)2 * (mb + 1) * (mb + 1) * sizeof(double)));
     c.coef = static_cast<double*>(ar.take(2 * NDQ_MAX_MODES * sizeof(double)));
     c.scal = static_cast<double*>(ar.take(64 * sizeof(double)));
+    c.gpart = static_cast<double*>(ar.take(gram_partials_bytes(g, nkeep, nkeep)));
+    c.gout = static_cast<double*>(ar.take(2 * 64 * 64 * sizeof(double)));
     if (ar.overflow) return fail(NDQ_ENOMEM, "low modes: workspace too small (need %zu bytes)", ar.used);
     const double b = lam_max * lam_max;
     const double tol = p->tol > 0 ? p->tol : 1e-10;

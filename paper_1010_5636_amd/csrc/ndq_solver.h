@@ -75,6 +75,12 @@ int dot(const ndq_geom* g, const ndq_spinor* x, const ndq_spinor* y, double* par
 int convert(const ndq_geom* g, const ndq_spinor* dst, const ndq_spinor* src, hipStream_t st);
 
 // Low modes: dots[k] = <u_k, v> for the nev packed F64 full spinors at `modes`.
+// G (device, na x nb complex, row-major) = A^H B for blocks of na and nb FP64
+// full spinor fields (contiguous, na, nb <= 64), on the matrix cores; partials
+// needs gram_partials_bytes(g, na, nb).
+size_t gram_partials_bytes(const ndq_geom* g, int na, int nb);
+int gram(const ndq_geom* g, const void* A, int na, const void* B, int nb, double* partials, double* G,
+         hipStream_t st);
 int mode_dots(const ndq_geom* g, const void* modes, int nev, const ndq_spinor* v, double* partials,
               double* dots, hipStream_t st);
 // coef_k = sc * (use_sign ? sign_k : 1) * c_k + sd * d_k (complex, device arrays of 2*nev doubles).

@@ -112,6 +112,8 @@ _SIG = {
                                 ctypes.POINTER(ctypes.c_int)]),
     "ndq_autotune": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                           ctypes.POINTER(_TuneResult), _P]),
+    "ndq_gram_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_int]),
+    "ndq_spinor_gram": (_I, [_P, ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P, _P, ctypes.c_size_t, _P]),
     "ndq_apply_Q_multi": (_I, [ctypes.POINTER(_QJob), ctypes.c_int32, _P]),
     "ndq_apply_dslash": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P]),
     "ndq_apply_Qhat_ee": (_I, [_P, ctypes.POINTER(_Gauge), _D, ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor),
@@ -309,6 +311,18 @@ def _canon(t: torch.Tensor, shape) -> torch.Tensor:
 def apply_Q(geom: Geometry, U: GaugeField, m: float, inp: SpinorField, out: SpinorField, stream=None):
     _check(lib().ndq_apply_Q(geom.handle, ctypes.byref(U.desc), float(m), ctypes.byref(inp.desc),
                              ctypes.byref(out.desc), _stream(stream)))
+
+
+def spinor_gram(geom: Geometry, A: SpinorField, B: SpinorField, stream=None) -> torch.Tensor:
+    """G[i][j] = <A_i, B_j> for blocks of F64 FULL fields (matrix cores); complex128 [na, nb] on the GPU."""
+    n = int(lib().ndq_gram_workspace_bytes(geom.handle, A.nrhs, B.nrhs))
+    if n == 0:
+        raise NdqError(-1, "bad block sizes for ndq_spinor_gram")
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    G = torch.empty((A.nrhs, B.nrhs), dtype=torch.complex128, device="cuda")
+    _check(lib().ndq_spinor_gram(geom.handle, ctypes.byref(A.desc), ctypes.byref(B.desc), _ptr(G), _ptr(ws), n,
+                                 _stream(stream)))
+    return G
 
 
 def apply_Q_multi(jobs, stream=None):
