@@ -178,6 +178,33 @@ def solve_leg(log):
         log(f"solve leg: {name} {el:.2f} s, residual {st['residual']:.2e}, outer {st['outer']}, "
             f"inner {st['inner']}, Q applies {st['q_applies']}")
         del x
+    # algorithmic bytes of the Q applies alone (links once, spinor in and out
+    # once per apply: 384 B/site F32-12, 200 F16-12, 960 F64-18), counted at the
+    # inner precision for the mixed runs (the FP64 outer applies are ~2% of them)
+    qbytes = {"mixed_f32": 384, "mixed_f16": 200, "fp64": 960}
+    for name, r in runs.items():
+        rb = r["q_applies"] * qbytes[name] * v
+        r["q_alg_bytes"] = rb
+        r["q_roofline_s"] = round(rb / (HBM_PEAK_GBS * 1e9), 4)
+        r["frac_of_roofline"] = round(rb / (HBM_PEAK_GBS * 1e9) / r["seconds"], 4)
+    # the paper's unit: time per site per Clenshaw step (one step = 2 Q applies
+    # with fused vector updates), on one polynomial sign apply
+    tau = {}
+    for name, prec, Uf, ap in (("f32", ndq.F32, U32, ap_lo), ("f64", ndq.F64, U64, ap64)):
+        ov = ndq.Overlap(g, M, ap, LAM_MAX)
+        xs = ndq.SpinorField.pack(g, torch.from_numpy(synthetic.spinor(v)).to(dev), prec, ndq.FULL)
+        ys = xs.like()
+        ndq.apply_sign(g, Uf, ov, xs, ys)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            ndq.apply_sign(g, Uf, ov, xs, ys)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / 3
+        tau[name] = {"degree": ap.n, "sign_ms": round(el * 1e3, 3), "tau_us": round(el / (ap.n * v) * 1e6, 6)}
+        del ov, xs, ys
+    out["clenshaw_tau"] = {"unit": "microseconds per site per Clenshaw step", **tau,
+                           "paper_context": "GTX285: 0.038 (single), 0.090 (double); Core2 SSE2: 0.877 / 1.459"}
     out["runs"] = runs
     out["speedup_mixed_f32_vs_fp64"] = round(runs["fp64"]["seconds"] / runs["mixed_f32"]["seconds"], 3)
     out["speedup_mixed_f16_vs_fp64"] = round(runs["fp64"]["seconds"] / runs["mixed_f16"]["seconds"], 3)
@@ -503,8 +530,12 @@ def main():
         k_avg = ms_total * 1e-3 / args.steps
         gflops = FLOP_PER_SITE * vh * args.steps / (ms_total * 1e-3) / 1e9
         alg_bytes = bps * vh
+        # the no-reuse count (8 neighbour spinors and 8 links per output site,
+        # plus the output), as GPU lattice codes often quote it
+        noreuse = (8 * (SPINOR_BYTES[sp] + recon * LINK_REAL_BYTES[lp]) + SPINOR_BYTES[sp]) * vh
         results[name] = {
             "gflops": round(gflops, 1),
+            "effective_gbs_no_reuse": noreuse / k_avg / 1e9,
             "ms_per_step": ms_total / args.steps,
             "wall_s": wall,
             "kernel_us_avg": k_avg * 1e6,
@@ -516,6 +547,33 @@ def main():
             "launch": launch,
             "autotune_us": None if tune is None else {k: round(t, 3) for k, t in tune["us"].items()},
         }
+        if (name, sp, lp, recon) == fmts[0] and not args.graph:
+            # the even-site Schur operator Qhat_ee (two dslashes and the site
+            # term) and the dslash replayed from a captured graph of 2 x nsets launches
+            tmps = [e.like(parity=ndq.ODD) for (_, e, _) in sets]
+            outs = [e.like() for (_, e, _) in sets]
+            it = {"k": 0}
+
+            def qhat():
+                k = it["k"] % nsets
+                U, e, _ = sets[k]
+                ndq.apply_Qhat_ee(g, U, M, e, outs[k], tmps[k])
+                it["k"] += 1
+
+            for _ in range(nsets):
+                qhat()
+            results[name]["qhat_ee_us"] = _time_events(qhat, 500) * 1e3
+            del tmps, outs
+            gph = torch.cuda.CUDAGraph()
+            cs = torch.cuda.Stream()
+            with torch.cuda.stream(cs):
+                with torch.cuda.graph(gph, stream=cs):
+                    for k in range(2 * nsets):
+                        step(k)
+            torch.cuda.synchronize()
+            gph.replay()
+            results[name]["graph_replay_us"] = _time_events(gph.replay, max(1, 1000 // (2 * nsets))) * 1e3 / (2 * nsets)
+            del gph
         del sets, graph
         torch.cuda.synchronize()
 
