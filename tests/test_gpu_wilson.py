@@ -210,3 +210,71 @@ def test_launch_shapes_agree(block, xcd):
     finally:
         ndq.ndq.set_launch(0, True)
     assert rel_l2(y.unpack().cpu().numpy()[0], ref) <= 1e-13
+
+
+BENCH_FORMATS = [(ndq.F32, ndq.F32, 12), (ndq.F32, ndq.F32, 18), (ndq.F32, ndq.F32, 8), (ndq.F64, ndq.F64, 18),
+                 (ndq.F16, ndq.F16, 12)]
+_DSLASH_REF = {}
+
+
+def dslash_ref_16c32(out_parity):
+    """Oracle even/odd dslash on the 16^3 x 32 benchmark lattice (cached)."""
+    if out_parity not in _DSLASH_REF:
+        dims = (32, 16, 16, 16)
+        u, _, _ = problem(dims)
+        psi = synthetic.spinor(geometry.volume(dims) // 2, seed=91 + out_parity)
+        _DSLASH_REF[out_parity] = (u, psi, dirac.dslash(u, psi, dims, out_parity))
+    return _DSLASH_REF[out_parity]
+
+
+@pytest.mark.parametrize("fmt", BENCH_FORMATS)
+@pytest.mark.parametrize("block,xcd", [(0, 1), (0, 0), (64, 1), (128, 1), (256, 1), (256, 0)])
+@pytest.mark.parametrize("out_parity", [ndq.EVEN, ndq.ODD])
+def test_dslash_full_size_16c32_every_shape(fmt, block, xcd, out_parity):
+    """The benchmarked operator (even/odd dslash on 16^3 x 32, every format) in every
+    launch shape the autotuner can pick, against the oracle over all sites."""
+    sp, lp, recon = fmt
+    dims = (32, 16, 16, 16)
+    u, psi, ref = dslash_ref_16c32(out_parity)
+    g = ndq.Geometry(dims)
+    U = ndq.GaugeField.pack(g, cu(u), lp, recon)
+    x = ndq.SpinorField.pack(g, cu(psi), sp, 1 - out_parity)
+    y = x.like(parity=out_parity)
+    try:
+        ndq.set_launch_for(sp, lp, recon, block, bool(xcd))
+        ndq.apply_dslash(g, U, x, y)
+    finally:
+        ndq.set_launch(0, True)
+    assert rel_l2(y.unpack().cpu().numpy()[0], ref) <= tol(sp, lp)
+
+
+@pytest.mark.parametrize("fmt", [(ndq.F64, ndq.F64, 18), (ndq.F32, ndq.F32, 12), (ndq.F16, ndq.F16, 12)])
+def test_apply_Q_sampled_24c48(fmt):
+    """Q on the 24^3 x 48 solve lattice in the solver's formats, checked at 200
+    sampled sites (and every face of the lattice) against the oracle's per-site Eq. 1."""
+    sp, lp, recon = fmt
+    dims = (48, 24, 24, 24)
+    v = geometry.volume(dims)
+    u, psi, _ = _big_24c48()
+    g = ndq.Geometry(dims)
+    U = ndq.GaugeField.pack(g, cu(u), lp, recon)
+    x = ndq.SpinorField.pack(g, cu(psi), sp, ndq.FULL)
+    y = x.like()
+    ndq.apply_Q(g, U, M, x, y)
+    rng = np.random.default_rng(17)
+    corners = np.array([[0, 0, 0, 0], [47, 23, 23, 23], [0, 23, 0, 23], [47, 0, 11, 0]])
+    sites = np.concatenate([geometry.lex_of(dims, corners), rng.integers(0, v, 200)])
+    got = y.unpack()[0][torch.from_numpy(sites).to("cuda")].cpu().numpy()
+    ref = dirac.apply_Q_at(u, lambda i: psi[i], M, dims, sites)
+    assert rel_l2(got, ref) <= tol(sp, lp)
+
+
+_BIG = {}
+
+
+def _big_24c48():
+    if "f" not in _BIG:
+        dims = (48, 24, 24, 24)
+        v = geometry.volume(dims)
+        _BIG["f"] = (synthetic.gauge_field(dims), synthetic.spinor(v, seed=1002), None)
+    return _BIG["f"]
