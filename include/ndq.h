@@ -271,10 +271,18 @@ typedef struct {
     double tol;           /* stop when every rho_k <= tol * lam_max                          */
     int32_t max_restarts; /* iterations / restart cycles (<= 0: 200 subspace, 100 Lanczos)     */
     int32_t method;       /* NDQ_LM_SUBSPACE (block Chebyshev-filtered subspace iteration,
-                             adaptive filter) or NDQ_LM_LANCZOS (thick-restart Lanczos)       */
+                             adaptive filter), NDQ_LM_LANCZOS (thick-restart Lanczos) or
+                             NDQ_LM_RITZ (the paper's Ritz-functional minimisation of Q^2:
+                             conjugate-gradient sweeps over the nev + 1 vectors, each kept
+                             orthogonal to the ones before, alternating with Rayleigh-Ritz of
+                             Q; max_restarts caps the CG steps per vector, default 5000)      */
+    int32_t nev_min;      /* 0: use all nev modes.  1 <= nev_min <= nev: choose the number l of
+                             modes to project in [nev_min, nev] where the relative gap
+                             |nu_(l+1)| / |nu_l| to the next mode is largest (Sec. 2.3: the gap
+                             should not be accidentally small); reported as nev_used          */
 } ndq_lowmode_params;
 
-enum { NDQ_LM_SUBSPACE = 0, NDQ_LM_LANCZOS = 1 };
+enum { NDQ_LM_SUBSPACE = 0, NDQ_LM_LANCZOS = 1, NDQ_LM_RITZ = 2 };
 
 typedef struct {
     double lam_next;      /* |Q u| of the guard vector u (the next Ritz vector after the
@@ -289,8 +297,11 @@ typedef struct {
     int64_t q_applies;
     double max_rho;       /* largest rho_k of the returned modes                             */
     double rho_next;      /* from the guard residue r = |Q^2 u - lam_next^2 u|: Q has an
-                             eigenvalue with |lambda| >= lam_next - rho_next = sqrt(lam_next^2 - r) */
+                             eigenvalue with |lambda| >= lam_next - rho_next = sqrt(lam_next^2 - r);
+                             with nev_used < nev: lam_next = |nu_(l+1)|, rho_next = rho_(l+1) */
     double seconds;
+    int32_t nev_used;     /* number l of modes to project (nev unless nev_min chose fewer);
+                             kappa and bounds refer to the first l modes                      */
 } ndq_lowmode_info;
 
 size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params* p);

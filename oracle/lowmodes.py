@@ -13,8 +13,11 @@ Sec. 2.3 of the paper:
 * |P_+- - (P_+-)_exact| <= kappa (1 + 2 kappa) / (1 - 2 kappa (1 + 2 kappa)) (Eq. 10);
 * |D_N^m(approx) - D_N^m| <= (2/a)(1 + s - a m / 2)(kappa_+ + kappa_-) (Eq. 12).
 
-The paper finds V with a Ritz-functional minimisation; here V comes either
-from a dense eigen-decomposition (small lattices) or from the caller.
+The paper finds V by minimising the Ritz functional of Q^2; ``ritz_lowmodes``
+does that literally (conjugate gradients on the Rayleigh quotient with exact
+line minimisation, one mode after the other, each kept orthogonal to the
+modes already found), ``dense_lowmodes`` takes V from a dense
+eigen-decomposition (small lattices).
 """
 from __future__ import annotations
 
@@ -89,3 +92,68 @@ def projector_bound(kappa: float) -> float:
 def dn_bound(kappa_p: float, kappa_m: float, s: float, mq: float, a: float = 1.0) -> float:
     """Eq. 12: (2/a)(1 + s - a m / 2)(kappa_+ + kappa_-)."""
     return (2.0 / a) * (1.0 + s - a * mq / 2.0) * (kappa_p + kappa_m)
+
+
+def _vdot(a, b):
+    return np.vdot(a.ravel(), b.ravel())
+
+
+def ritz_minimise(apply_a, x0, lower, tol: float, max_iter: int = 10000):
+    """Minimise the Ritz functional mu(x) = <x, A x> / <x, x> of a Hermitian
+    positive A over x orthogonal to the orthonormal vectors ``lower``.
+
+    Conjugate gradients on the unit sphere: the gradient direction is
+    g = (A x - mu x) with the components along ``lower`` removed; each step
+    minimises mu exactly on span(x, p) (the smaller eigenvalue of the 2 x 2
+    Rayleigh-quotient matrix of that plane); the next direction is
+    g + beta p with beta = |g_new|^2 / |g_old|^2.  Stops when |g| <= tol.
+    Returns (x unit, mu, |g|, iterations).
+    """
+    def proj(v):
+        for u in lower:
+            v = v - _vdot(u, v) * u
+        return v
+
+    x = proj(np.array(x0, dtype=np.complex128))
+    x = x / np.linalg.norm(x.ravel())
+    y = apply_a(x)
+    mu = _vdot(x, y).real
+    g = proj(y - mu * x)
+    g2 = _vdot(g, g).real
+    p = g.copy()
+    it = 0
+    while np.sqrt(g2) > tol and it < max_iter:
+        pp = p - _vdot(x, p) * x
+        ph = pp / np.linalg.norm(pp.ravel())
+        z = apply_a(ph)
+        a, b, c = mu, _vdot(x, z).real, _vdot(ph, z).real
+        # mu(t) = a cos^2 t + 2 b sin t cos t + c sin^2 t is smallest at
+        # (cos 2t, sin 2t) proportional to ((c - a) / 2, -b)
+        t = 0.5 * np.arctan2(-b, 0.5 * (c - a))
+        cs, sn = np.cos(t), np.sin(t)
+        x = cs * x + sn * ph
+        y = cs * y + sn * z
+        x = proj(x)
+        nx = np.linalg.norm(x.ravel())
+        x, y = x / nx, y / nx
+        mu = _vdot(x, y).real
+        g_new = proj(y - mu * x)
+        g2_new = _vdot(g_new, g_new).real
+        p = g_new + (g2_new / g2) * pp
+        g, g2 = g_new, g2_new
+        it += 1
+    return x, mu, float(np.sqrt(g2)), it
+
+
+def ritz_lowmodes(apply_a, starts, nev: int, tol: float, max_iter: int = 10000):
+    """The nev lowest eigenpairs of A (Sec. 2.3: the Ritz functional of Q^2),
+    one after the other, mode k minimised orthogonally to modes 0..k-1 from the
+    start vector starts[k].  Returns (mu[nev] ascending, x[nev, ...], |g|[nev])."""
+    modes, mus, gs = [], [], []
+    for k in range(nev):
+        x, mu, gn, _ = ritz_minimise(apply_a, starts[k], modes, tol, max_iter)
+        modes.append(x)
+        mus.append(mu)
+        gs.append(gn)
+    return np.array(mus), np.stack(modes), np.array(gs)
+

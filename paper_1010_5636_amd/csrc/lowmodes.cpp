@@ -311,6 +311,104 @@ int orthonormalise(LmCtx& c, char* X, int nb) {
     return NDQ_OK;
 }
 
+// Minimise the Ritz functional mu(x) = <x, A x> / |x|^2, A = Q^2, over x
+// orthogonal to the k orthonormal vectors at `base` (Sec. 2.3): conjugate
+// gradients on the unit sphere, each step minimising mu exactly in the plane
+// of x and the search direction; g = (A x - mu x) with the lower vectors
+// removed, next direction g + (|g_new|^2 / |g|^2) p.  Stops when |g| <= tol
+// (times sqrt(mu) if tol_times_sqrt_mu).  x is vector k of `base` (start on
+// entry, minimiser on exit); scratch: 5 vectors at `scr`.
+int ritz_minimise(LmCtx& c, char* base, int k, char* scr, double tol, bool tol_times_sqrt_mu, int max_iter, int* iters,
+                  double* mu_out, double* gnorm_out) {
+    int rc;
+    const ndq_geom* g = c.g;
+    const ndq_spinor x = c.vec(base, k);
+    const ndq_spinor y = c.vec(scr, 0), gr = c.vec(scr, 1), p = c.vec(scr, 2), pp = c.vec(scr, 3), z = c.vec(scr, 4);
+    std::vector<cd> h;
+    auto proj = [&](const ndq_spinor* v) -> int {
+        if (k == 0) return NDQ_OK;
+        int e = c.dots_to_host(base, k, v, h);
+        if (!e) e = c.subtract(base, k, h, v);
+        return e;
+    };
+    auto dot1 = [&](const ndq_spinor* a, const ndq_spinor* b, cd* out) -> int {
+        std::vector<cd> d1;
+        int e = c.dots_to_host(static_cast<char*>(a->data), 1, b, d1);
+        if (!e) *out = d1[0];
+        return e;
+    };
+    auto comb = [&](const ndq_spinor* dst, double ca, const ndq_spinor* a, double cb, const ndq_spinor* b) -> int {
+        const ndq_spinor* v[2] = {a, b};
+        const Coef cf[2] = {Coef{ca, nullptr}, Coef{cb, nullptr}};
+        return lincomb(g, NDQ_F64, dst, b ? 2 : 1, v, cf, nullptr, nullptr, c.st);
+    };
+    if ((rc = proj(&x))) return rc;
+    double n2;
+    if ((rc = c.norm2(&x, &n2))) return rc;
+    if (!(n2 > 0) || !isfinite(n2)) return fail(NDQ_ENAN, "low modes (Ritz): start vector lost");
+    if ((rc = c.copy(&x, &x, 1.0 / sqrt(n2)))) return rc;
+    if ((rc = apply_A(c, &x, &y))) return rc;
+    cd t;
+    if ((rc = dot1(&x, &y, &t))) return rc;
+    double mu = t.real();
+    if ((rc = comb(&gr, 1.0, &y, -mu, &x))) return rc;
+    if ((rc = proj(&gr))) return rc;
+    double g2;
+    if ((rc = c.norm2(&gr, &g2))) return rc;
+    if ((rc = c.copy(&p, &gr))) return rc;
+    int it = 0;
+    auto limit = [&]() { return tol_times_sqrt_mu ? tol * sqrt(std::max(mu, 0.0)) : tol; };
+    while (sqrt(g2) > limit() && it < max_iter) {
+        // pp = p - <x, p> x, ph = pp / |pp|
+        if ((rc = dot1(&x, &p, &t))) return rc;
+        {
+            // complex coefficient: pp = p - t x as a rank-1 update
+            const std::vector<cd> hh(1, t);
+            if ((rc = c.copy(&pp, &p))) return rc;
+            if ((rc = c.subtract(static_cast<char*>(x.data), 1, hh, &pp))) return rc;
+        }
+        double pn2;
+        if ((rc = c.norm2(&pp, &pn2))) return rc;
+        if (!(pn2 > 0)) break;   // direction parallel to x: converged as far as it goes
+        const double pinv = 1.0 / sqrt(pn2);
+        if ((rc = c.copy(&z, &pp, pinv))) return rc;       // z <- ph (temporarily)
+        if ((rc = apply_A(c, &z, &c.X1))) return rc;       // X1 <- A ph
+        cd bz, cz;
+        if ((rc = dot1(&x, &c.X1, &bz))) return rc;
+        if ((rc = dot1(&z, &c.X1, &cz))) return rc;
+        const double a = mu, b = bz.real(), cc = cz.real();
+        const double th = 0.5 * atan2(-b, 0.5 * (cc - a));
+        const double cs = cos(th), sn = sin(th);
+        if ((rc = comb(&x, cs, &x, sn, &z))) return rc;      // x <- cs x + sn ph
+        if ((rc = comb(&y, cs, &y, sn, &c.X1))) return rc;   // y <- cs y + sn A ph
+        if ((rc = proj(&x))) return rc;
+        if ((rc = c.norm2(&x, &n2))) return rc;
+        const double ninv = 1.0 / sqrt(n2);
+        if ((rc = c.copy(&x, &x, ninv))) return rc;
+        if ((rc = c.copy(&y, &y, ninv))) return rc;
+        if ((rc = dot1(&x, &y, &t))) return rc;
+        mu = t.real();
+        if ((rc = comb(&gr, 1.0, &y, -mu, &x))) return rc;
+        if ((rc = proj(&gr))) return rc;
+        double g2n;
+        if ((rc = c.norm2(&gr, &g2n))) return rc;
+        if (!isfinite(g2n)) return fail(NDQ_ENAN, "low modes (Ritz): NaN in the minimisation");
+        if ((rc = comb(&p, 1.0, &gr, g2n / g2, &pp))) return rc;
+        g2 = g2n;
+        ++it;
+        // every 50 steps recompute A x (the update of y accumulates rounding)
+        if (it % 50 == 0) {
+            if ((rc = apply_A(c, &x, &y))) return rc;
+            if ((rc = dot1(&x, &y, &t))) return rc;
+            mu = t.real();
+        }
+    }
+    *iters = it;
+    *mu_out = mu;
+    *gnorm_out = sqrt(g2);
+    return NDQ_OK;
+}
+
 // Degree of the filter T_d on [a, b]: large enough to gain a factor ~2e3 at the
 // guard eigenvalue per application, but with T_d(x(0)) <= 1e10 (A = Q^2 >= 0, so
 // no eigenvalue is amplified more): a larger contrast than ~1/eps would leave the
@@ -340,13 +438,13 @@ size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params*
     const int m = p->method == NDQ_LM_LANCZOS ? p->basis : nkeep;
     if (m < 2) return 0;
     Arena ar{nullptr, 0};
-    ar.take(vb * (m + 1));          // VA
-    ar.take(vb * (m + 1));          // VB
+    ar.take(vb * std::max(m + 1, 5));       // VA
+    ar.take(vb * std::max(m + 1, 5));       // VB (Ritz: 5 work vectors)
     ar.take(vb * nkeep);            // W
     ar.take(vb * nkeep);            // WS
     ar.take(vb * (p->nev + 1));     // QU
     ar.take(vb * (p->nev + 1));     // UU
-    if (p->method != NDQ_LM_LANCZOS) ar.take(vb * nkeep);   // SB
+    if (p->method == NDQ_LM_SUBSPACE) ar.take(vb * nkeep);   // SB
     for (int i = 0; i < 3; ++i) ar.take(vb);
     ar.take(partials_capacity(g, 2 * NDQ_MAX_MODES));
     ar.take(2 * NDQ_MAX_MODES * sizeof(double));
@@ -368,7 +466,10 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     if (rc) return rc;
     if (U->prec != NDQ_F64 || start->prec != NDQ_F64) return fail(NDQ_EPREC, "low modes: FP64 links and start vector");
     const bool lanczos = p->method == NDQ_LM_LANCZOS;
-    if (p->method != NDQ_LM_SUBSPACE && !lanczos) return fail(NDQ_EINVAL, "low modes: unknown method %d", p->method);
+    const bool ritz = p->method == NDQ_LM_RITZ;
+    if (p->method != NDQ_LM_SUBSPACE && !lanczos && !ritz)
+        return fail(NDQ_EINVAL, "low modes: unknown method %d", p->method);
+    if (p->nev_min < 0 || p->nev_min > p->nev) return fail(NDQ_EINVAL, "low modes: nev_min must be in [0, nev]");
     const int nev = p->nev, nkeep = nev + std::max(p->nextra, 1);
     const int mb = lanczos ? p->basis : nkeep;
     if (nev < 1 || nkeep > NDQ_MAX_MODES || (lanczos && (mb > NDQ_MAX_MODES - 1 || mb < nkeep + 2)))
@@ -382,13 +483,13 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     c.st = as_stream(stream);
     c.vb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
     Arena ar{static_cast<char*>(ws), ws_bytes};
-    c.VA = static_cast<char*>(ar.take(c.vb * (mb + 1)));
-    c.VB = static_cast<char*>(ar.take(c.vb * (mb + 1)));
+    c.VA = static_cast<char*>(ar.take(c.vb * std::max(mb + 1, 5)));
+    c.VB = static_cast<char*>(ar.take(c.vb * std::max(mb + 1, 5)));
     c.W = static_cast<char*>(ar.take(c.vb * nkeep));
     char* WS = static_cast<char*>(ar.take(c.vb * nkeep));
     c.QU = static_cast<char*>(ar.take(c.vb * (nev + 1)));
     c.UU = static_cast<char*>(ar.take(c.vb * (nev + 1)));
-    if (!lanczos) c.SB = static_cast<char*>(ar.take(c.vb * nkeep));
+    if (p->method == NDQ_LM_SUBSPACE) c.SB = static_cast<char*>(ar.take(c.vb * nkeep));
     c.X0 = ws_spinor(ar, g, NDQ_F64);
     c.X1 = ws_spinor(ar, g, NDQ_F64);
     c.S = ws_spinor(ar, g, NDQ_F64);
@@ -403,7 +504,7 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     const double b = lam_max * lam_max;
     const double tol = p->tol > 0 ? p->tol : 1e-10;
     const double guard_tol = std::max(tol, 1e-6);
-    const int max_restarts = p->max_restarts > 0 ? p->max_restarts : (lanczos ? 100 : 200);
+    const int max_restarts = p->max_restarts > 0 ? p->max_restarts : (lanczos ? 100 : ritz ? 5000 : 200);
     const int nsel = nev + 1;
 
     double s2;
@@ -419,7 +520,42 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     char* XS = c.VB;
     char* W = c.W;
 
-    if (!lanczos) {
+    if (ritz) {
+        // ---- Ritz functional of Q^2 (the paper's method) with the acceleration
+        // of Kalkreuter and Simma: sweeps of conjugate-gradient minimisation over
+        // a block of nev + nextra vectors (vector i kept orthogonal to vectors
+        // 0..i-1, at most `inner` steps each), then the Rayleigh-Ritz step of Q in
+        // their span, which rotates the block onto Ritz vectors and decouples close
+        // modes.  The wanted nev and the guard must converge; the rest only help.
+        for (int i = 0; i < nkeep; ++i) {
+            const ndq_spinor xi = c.vec(X, i);
+            if ((rc = phase_copy(g, start, &xi, i, c.st))) return rc;
+        }
+        if ((rc = orthonormalise(c, X, nkeep))) return rc;
+        const int inner = 40;
+        const int max_sweeps = std::max(1, max_restarts / inner);
+        for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+            for (int i = 0; i < nkeep; ++i) {
+                // |(A - mu) x| ~ |lambda_j + nu| |(Q - nu) x| near an eigenvector: aim below the
+                // target; the Rayleigh-Ritz residues decide convergence
+                int iters = 0;
+                double mu = 0.0, gn = 0.0;
+                if (i < nev) rc = ritz_minimise(c, X, i, XS, 0.1 * tol * lam_max, true, inner, &iters, &mu, &gn);
+                else rc = ritz_minimise(c, X, i, XS, 0.5 * guard_tol * b, false, inner, &iters, &mu, &gn);
+                if (rc) return rc;
+                restarts += iters;
+            }
+            if ((rc = rayleigh_ritz_q(c, X, W, XS, WS, nkeep, nsel, true, rr))) return rc;
+            double max_rho = 0.0;
+            for (int k = 0; k < nev; ++k) max_rho = std::max(max_rho, rr.rho[k]);
+            if (max_rho <= tol * lam_max && rr.guard_res <= guard_tol * b) {
+                converged = true;
+                break;
+            }
+        }
+        a = 0.0;
+        d = 0;
+    } else if (!lanczos) {
         // ---- Chebyshev-filtered subspace iteration on a block of nkeep vectors
         for (int i = 0; i < nkeep; ++i) {
             const ndq_spinor xi = c.vec(X, i);
@@ -526,16 +662,35 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     }
     // guard: A has an eigenvalue in [theta - r, theta + r] (r = |A u - theta u|),
     // so |Q| has one at or above sqrt(theta - r) = lam_next - rho_next
-    const double lam_next = sqrt(std::max(rr.theta[nev], 0.0));
-    const double rho_next = lam_next - sqrt(std::max(rr.theta[nev] - rr.guard_res, 0.0));
+    double lam_next = sqrt(std::max(rr.theta[nev], 0.0));
+    double rho_next = lam_next - sqrt(std::max(rr.theta[nev] - rr.guard_res, 0.0));
+    // dynamic number of projected modes: the largest relative gap
+    // |nu_(l+1)| / |nu_l| for l in [nev_min, nev] (|nu_(nev+1)| = lam_next)
+    int l_used = nev;
+    if (p->nev_min >= 1 && p->nev_min < nev) {
+        double best = -1.0;
+        for (int l = p->nev_min; l <= nev; ++l) {
+            const double next = l < nev ? fabs(nu[l]) : lam_next;
+            const double ratio = next / std::max(fabs(nu[l - 1]), 1e-300);
+            if (ratio > best) {
+                best = ratio;
+                l_used = l;
+            }
+        }
+        if (l_used < nev) {
+            lam_next = fabs(nu[l_used]);
+            rho_next = rho[l_used];
+        }
+    }
     if (info) {
         memset(info, 0, sizeof(*info));
         info->lam_next = lam_next;
+        info->nev_used = l_used;
         // Eq. 9 with d_k = min(lam_next - |nu_k|, |nu_k| + min over opposite-sign |nu_j|)
         double kp2 = 0.0, km2 = 0.0;
-        for (int k = 0; k < nev; ++k) {
+        for (int k = 0; k < l_used; ++k) {
             double dk = lam_next - fabs(nu[k]);
-            for (int j = 0; j < nev; ++j)
+            for (int j = 0; j < l_used; ++j)
                 if ((nu[j] > 0) != (nu[k] > 0)) dk = std::min(dk, fabs(nu[k]) + fabs(nu[j]));
             const double q = dk > 0 ? rho[k] / dk : INFINITY;
             (nu[k] > 0 ? kp2 : km2) += q * q;

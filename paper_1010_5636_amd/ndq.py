@@ -22,7 +22,7 @@ F64, F32, F16 = 0, 1, 2
 EVEN, ODD, FULL = 0, 1, 2
 ZOLOTAREV, MINMAX_POLY = 0, 1
 LITERAL, SANDWICH = 0, 1
-LM_SUBSPACE, LM_LANCZOS = 0, 1
+LM_SUBSPACE, LM_LANCZOS, LM_RITZ = 0, 1, 2
 OP_SIGN, OP_DN, OP_SOLVE = 0, 1, 2
 
 STATUS = {0: "NDQ_OK", -1: "NDQ_EINVAL", -2: "NDQ_EDIMS", -3: "NDQ_EPREC", -4: "NDQ_ENOMEM",
@@ -72,14 +72,15 @@ class _Stats(ctypes.Structure):
 class _LmParams(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int32), ("nextra", ctypes.c_int32), ("basis", ctypes.c_int32),
                 ("cheb_degree", ctypes.c_int32), ("cheb_lo", ctypes.c_double), ("tol", ctypes.c_double),
-                ("max_restarts", ctypes.c_int32), ("method", ctypes.c_int32)]
+                ("max_restarts", ctypes.c_int32), ("method", ctypes.c_int32), ("nev_min", ctypes.c_int32)]
 
 
 class _LmInfo(ctypes.Structure):
     _fields_ = [("lam_next", ctypes.c_double), ("kappa_plus", ctypes.c_double), ("kappa_minus", ctypes.c_double),
                 ("bound_plus", ctypes.c_double), ("bound_minus", ctypes.c_double), ("cheb_lo", ctypes.c_double),
                 ("cheb_degree", ctypes.c_int32), ("restarts", ctypes.c_int32), ("q_applies", ctypes.c_int64),
-                ("max_rho", ctypes.c_double), ("rho_next", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("max_rho", ctypes.c_double), ("rho_next", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("nev_used", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -437,11 +438,11 @@ def apply_DN(geom: Geometry, U: GaugeField, ov: Overlap, inp: SpinorField, out: 
 
 def lowmodes_compute(geom: Geometry, U: GaugeField, m: float, lam_max: float, start: SpinorField, nev: int,
                      nextra: int = 8, basis: int = 0, cheb_degree: int = 0, cheb_lo: float = 0.0, tol: float = 1e-10,
-                     max_restarts: int = 0, method: int = 0, stream=None):
+                     max_restarts: int = 0, method: int = 0, nev_min: int = 0, stream=None):
     """Low modes of Q: returns (modes SpinorField (F64, FULL, nrhs=nev), nu, rho, info dict)."""
     import numpy as np
     basis = basis or min(63, nev + nextra + max(12, nev))
-    p = _LmParams(nev, nextra, basis, cheb_degree, cheb_lo, tol, max_restarts, method)
+    p = _LmParams(nev, nextra, basis, cheb_degree, cheb_lo, tol, max_restarts, method, nev_min)
     nbytes = int(lib().ndq_lowmodes_workspace_bytes(geom.handle, ctypes.byref(p)))
     if nbytes == 0:
         raise NdqError(-1, "bad low-mode parameters")

@@ -7,7 +7,8 @@
 * 8^4 random links, l = 12: residues recomputed by the oracle's stencil.
 * 4^4 free field, l = 48 (block method): the exactly 48-fold degenerate
   |lambda| = 0.6 eigenspace, projector against the exact one.
-Both methods (block subspace iteration, thick-restart Lanczos) are exercised.
+All three methods (block subspace iteration, thick-restart Lanczos, and the
+paper's Ritz-functional minimisation) are exercised.
 """
 import numpy as np
 import pytest
@@ -41,7 +42,7 @@ def run(dims, u, nev, nextra=8, tol=1e-11, basis=0, method=ndq.ndq.LM_SUBSPACE):
     return g, U, modes, nu, rho, info
 
 
-METHODS = [ndq.ndq.LM_SUBSPACE, ndq.ndq.LM_LANCZOS]
+METHODS = [ndq.ndq.LM_SUBSPACE, ndq.ndq.LM_LANCZOS, ndq.ndq.LM_RITZ]
 
 
 @pytest.fixture(scope="module")
@@ -123,3 +124,22 @@ def test_lowmodes_free_field_degenerate():
     pe = w[:, np.abs(np.abs(lam) - 0.6) < 1e-9]
     assert pe.shape[1] == 48
     assert np.linalg.norm(um.T @ um.conj() - pe @ pe.conj().T, 2) < 1e-9
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_dynamic_number_of_modes(dense4, method):
+    """nev_min: the number l of projected modes is the one in [nev_min, nev]
+    with the largest relative gap |nu_(l+1)| / |nu_l| (Sec. 2.3), checked
+    against the dense spectrum."""
+    nev, nev_min = 10, 4
+    g = ndq.Geometry((4, 4, 4, 4))
+    U = ndq.GaugeField.pack(g, cu(dense4["u"]), ndq.F64, 18)
+    start = ndq.SpinorField.pack(g, cu(synthetic.start_vector(256)), ndq.F64, ndq.FULL)
+    modes, nu, rho, info = ndq.lowmodes_compute(g, U, M, LMAX, start, nev, tol=1e-11, method=method,
+                                                nev_min=nev_min)
+    lam = np.abs(dense4["eig"][0][dense4["order"]])
+    ratios = [lam[l] / lam[l - 1] for l in range(nev_min, nev + 1)]
+    l_expect = nev_min + int(np.argmax(ratios))
+    assert info["nev_used"] == l_expect
+    assert abs(info["lam_next"] - lam[l_expect]) < 1e-8
+

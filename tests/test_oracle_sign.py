@@ -204,3 +204,37 @@ def test_grad_psi_vs_fd():
     fd = (force.action(u, psi + h * eta, M, dims) - force.action(u, psi - h * eta, M, dims)) / (2 * h)
     # dS = Re<grad, d psi> in the convention grad = 2 dS/d(psi-bar)
     assert abs(fd - np.vdot(g, eta).real) < 1e-7 * abs(fd)
+
+
+def test_ritz_functional_lowmodes(dense_random):
+    """The Ritz-functional minimisation reproduces the lowest eigenvalues of Q^2
+    from dense diagonalisation, with orthonormal vectors and small residues;
+    the Rayleigh-Ritz step of Q in their span gives the lowest |lambda| of Q."""
+    q = dense_random.Q
+    n = q.shape[0]
+    a = q @ q
+    rng = np.random.default_rng(3)
+    starts = rng.normal(size=(6, n)) + 1j * rng.normal(size=(6, n))
+    mu, x, g = lowmodes.ritz_lowmodes(lambda v: a @ v, starts, 6, tol=1e-10)
+    lam2 = np.sort(dense_random.lam ** 2)[:6]
+    assert np.allclose(mu, lam2, rtol=0, atol=1e-12)
+    assert np.abs(x.conj() @ x.T - np.eye(6)).max() < 1e-12
+    assert np.all(g <= 1e-10)
+    for xi, mi in zip(x, mu):
+        assert np.linalg.norm(a @ xi - mi * xi) <= 1e-9
+    nu, u = lowmodes.rayleigh_ritz(lambda v: q @ v, x)
+    order = np.argsort(np.abs(dense_random.lam), kind="stable")[:6]
+    assert np.allclose(np.sort(np.abs(nu)), np.sort(np.abs(dense_random.lam[order])), atol=1e-10)
+
+
+def test_ritz_functional_free_field_degenerate(dense_cold):
+    """On the free field the lowest eigenvalue of Q^2 (0.36) is 48-fold: every
+    minimisation lands in that eigenspace."""
+    q = dense_cold.Q
+    a = q @ q
+    rng = np.random.default_rng(4)
+    starts = rng.normal(size=(4, q.shape[0])) + 1j * rng.normal(size=(4, q.shape[0]))
+    mu, x, _ = lowmodes.ritz_lowmodes(lambda v: a @ v, starts, 4, tol=1e-11)
+    assert np.allclose(mu, 0.36, atol=1e-12)
+    pe = dense_cold.W[:, np.abs(np.abs(dense_cold.lam) - 0.6) < 1e-9]
+    assert np.linalg.norm(x.T - pe @ (pe.conj().T @ x.T)) < 1e-9
