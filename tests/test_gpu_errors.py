@@ -1,0 +1,114 @@
+"""Error paths of the C ABI on the GPU, forced from the host (iteration limits,
+undersized workspaces, bad descriptors): every call returns its documented
+status, leaves a message, and the library keeps working afterwards."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import dirac, geometry
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1010_5636_amd as ndq  # noqa: E402
+from paper_1010_5636_amd.ndq import lib, _ptr  # noqa: E402
+
+M = -1.4
+LMAX = 6.6
+DIMS = (4, 4, 4, 4)
+ENOMEM, ENOCONV = -4, -6
+
+
+def cu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def fields():
+    g = ndq.Geometry(DIMS)
+    u = synthetic.gauge_field(DIMS)
+    v = geometry.volume(DIMS)
+    return {"g": g, "u": u, "U": ndq.GaugeField.pack(g, cu(u), ndq.F64, 18),
+            "psi": synthetic.spinor(v, seed=5), "v": v}
+
+
+def still_works(f):
+    x = ndq.SpinorField.pack(f["g"], cu(f["psi"]), ndq.F64, ndq.FULL)
+    y = x.like()
+    ndq.apply_Q(f["g"], f["U"], M, x, y)
+    ref = dirac.apply_Q(f["u"], f["psi"], M, DIMS)
+    got = y.unpack().cpu().numpy()[0]
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_solve_outer_limit(fields):
+    """Too few outer steps for the tolerance: ENOCONV, with the best iterate in x."""
+    f = fields
+    ap = ndq.Approx(ndq.ZOLOTAREV, 0.08, 10)
+    ov = ndq.Overlap(f["g"], M, ap, LMAX, mq=0.05, tol=1e-12)
+    b = ndq.SpinorField.pack(f["g"], cu(f["psi"]), ndq.F64, ndq.FULL)
+    x = b.like()
+    x.buf.zero_()
+    with pytest.raises(ndq.NdqError) as e:
+        ndq.solve_DN(f["g"], f["U"], ov, b, x, tol=1e-14, max_outer=1, max_inner=5)
+    assert e.value.status == ENOCONV
+    assert "solve" in str(e.value).lower() or e.value.args
+    assert torch.isfinite(x.unpack()).all()
+    still_works(f)
+
+
+def test_lowmodes_iteration_limit(fields):
+    f = fields
+    start = ndq.SpinorField.pack(f["g"], cu(synthetic.start_vector(f["v"])), ndq.F64, ndq.FULL)
+    for method in (ndq.ndq.LM_SUBSPACE, ndq.ndq.LM_LANCZOS, ndq.ndq.LM_RITZ):
+        with pytest.raises(ndq.NdqError) as e:
+            ndq.lowmodes_compute(f["g"], f["U"], M, LMAX, start, 8, tol=1e-14, max_restarts=1, method=method)
+        assert e.value.status == ENOCONV
+    still_works(f)
+
+
+def test_undersized_workspaces(fields):
+    f = fields
+    ap = ndq.Approx(ndq.MINMAX_POLY, 0.01, 20)
+    ov = ndq.Overlap(f["g"], M, ap, LMAX)
+    x = ndq.SpinorField.pack(f["g"], cu(f["psi"]), ndq.F64, ndq.FULL)
+    y = x.like()
+    need = int(lib().ndq_workspace_bytes(f["g"].handle, ctypes.byref(ov.p), ndq.F64, 0))
+    ws = torch.empty(need // 2, dtype=torch.uint8, device="cuda")
+    st = ndq.ndq._Stats()
+    rc = lib().ndq_apply_sign(f["g"].handle, ctypes.byref(f["U"].desc), ctypes.byref(ov.p), ctypes.byref(x.desc),
+                              ctypes.byref(y.desc), _ptr(ws), ws.numel(), ctypes.byref(st), None)
+    assert rc == ENOMEM
+    assert "workspace" in lib().ndq_last_error().decode()
+    A = ndq.SpinorField.pack(f["g"], cu(synthetic.spinor(f["v"], nrhs=3)), ndq.F64, ndq.FULL)
+    G = torch.empty((3, 3), dtype=torch.complex128, device="cuda")
+    rc = lib().ndq_spinor_gram(f["g"].handle, ctypes.byref(A.desc), ctypes.byref(A.desc), _ptr(G), _ptr(ws), 16, None)
+    assert rc == ENOMEM
+    still_works(f)
+
+
+def test_bad_descriptors(fields):
+    f = fields
+    x = ndq.SpinorField.pack(f["g"], cu(f["psi"]), ndq.F64, ndq.FULL)
+    e = ndq.SpinorField(f["g"], ndq.F64, ndq.EVEN)
+    # wrong parity for Q, aliasing in and out, mismatched precision
+    with pytest.raises(ndq.NdqError):
+        ndq.apply_Q(f["g"], f["U"], M, e, e.like())
+    with pytest.raises(ndq.NdqError):
+        ndq.apply_Q(f["g"], f["U"], M, x, x)
+    with pytest.raises(ndq.NdqError):
+        ndq.apply_Q(f["g"], f["U"], M, x, ndq.SpinorField(f["g"], ndq.F32, ndq.FULL))
+    # F32 spinors with F64 links
+    x32 = ndq.SpinorField.pack(f["g"], cu(f["psi"]), ndq.F32, ndq.FULL)
+    with pytest.raises(ndq.NdqError):
+        ndq.apply_Q(f["g"], f["U"], M, x32, x32.like())
+    # an odd output for an odd input (dslash maps parity 1 - p to p)
+    o = ndq.SpinorField(f["g"], ndq.F64, ndq.ODD)
+    with pytest.raises(ndq.NdqError):
+        ndq.apply_dslash(f["g"], f["U"], o, o.like())
+    still_works(f)
