@@ -22,8 +22,12 @@
  *     massive operator D_N^m = (1 - abar mq/2) D_N + mq (the form bounded by Eq. 12).
  *
  * Memory and ownership:
- *   - every device buffer is allocated and owned by the caller (the library
- *     never allocates device memory); *_bytes() queries give the sizes;
+ *   - every device buffer of a compute call is allocated and owned by the
+ *     caller; *_bytes() queries give the sizes.  Only set-up utilities
+ *     allocate: ndq_autotune (its rotating field copies, freed before it
+ *     returns), ndq_gauge_pack for 8-real links (a 4-byte pinned host flag),
+ *     and the graph replay of ndq_overlap_params.graph (a capture stream per
+ *     device and up to four instantiated graphs per host thread);
  *   - "canonical" buffers are complex128 (interleaved re, im doubles) in device
  *     memory: gauge [V][4 mu][3 row][3 col] in lexicographic order; spinor
  *     [nrhs][nsites][4 spin][3 colour] with nsites = V (lexicographic order)
