@@ -140,7 +140,9 @@ def solve_leg(log):
     t_fields = time.perf_counter() - t0
     log(f"solve leg: fields {t_fields:.1f} s")
     t0 = time.perf_counter()
-    modes, nu, rho, info = ndq.lowmodes_compute(g, U64, M, LAM_MAX, start, SOLVE_NEV, tol=1e-11)
+    # a block of 20 + 40 vectors: the 20 lowest modes sit in a dense cluster, and
+    # the larger block converges in fewer filter steps (measured 36 s vs 55 s with 20 + 8)
+    modes, nu, rho, info = ndq.lowmodes_compute(g, U64, M, LAM_MAX, start, SOLVE_NEV, nextra=40, tol=1e-11)
     t_modes = time.perf_counter() - t0
     log(f"solve leg: low modes {t_modes:.1f} s, {info['q_applies']} Q applies, lam_next {info['lam_next']:.5f}")
     k = (info["lam_next"] - info["rho_next"]) / LAM_MAX
@@ -158,7 +160,7 @@ def solve_leg(log):
            "lowmodes": {"nev": SOLVE_NEV, "nu_abs_min": float(np.abs(nu).min()), "nu_abs_max": float(np.abs(nu).max()),
                         "lam_next": info["lam_next"], "max_rho": info["max_rho"], "kappa_plus": info["kappa_plus"],
                         "kappa_minus": info["kappa_minus"], "q_applies": info["q_applies"],
-                        "restarts": info["restarts"], "cheb_degree": info["cheb_degree"]},
+                        "restarts": info["restarts"], "cheb_degree": info["cheb_degree"], "block": SOLVE_NEV + 40},
            "approximant": {"kind": "minimax polynomial (Clenshaw)", "eps": eps, "degree_fp64": ap64.n,
                            "delta_fp64": ap64.delta, "degree_inner": ap_lo.n, "delta_inner": ap_lo.delta}}
     runs = {}
