@@ -59,7 +59,7 @@ def kernel_name(launch):
 
 def read_traffic(fmt_name, launch):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source at this launch shape; else None."""
     path = os.path.join(ROOT, "profiles", "dslash_16c32_traffic.json")
     if not os.path.exists(path):
         return None
@@ -68,13 +68,8 @@ def read_traffic(fmt_name, launch):
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    from paper_1010_5636_amd.profiling import kernel_hash
-    if rec.get("kernel_hash") != kernel_hash():
-        return None
-    ent = rec.get("formats", {}).get(fmt_name)
-    if ent is None or ent.get("launch") != launch:
-        return None
-    return ent.get("bytes_per_launch")
+    from paper_1010_5636_amd.profiling import lookup
+    return lookup(rec, fmt_name, launch)
 
 
 def cpu_baseline(max_seconds=20.0):

@@ -186,16 +186,30 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned lin, unsigned total) {
     return start + (lin >> 3);
 }
 
+// Launch position -> (parity slot y, position within that parity).  With both
+// parities in one launch (the full Q) the two parities of a tile take adjacent
+// positions, so after the XCD remap they run on the same XCD at about the same
+// time: the links one parity reads as forward links the other reads as backward
+// links, and the second read finds them in that XCD's L2.  The position is then
+// mapped to a tile by order_tile.
+__device__ __forceinline__ int32_t parity_slot(unsigned lin, int& y) {
+    if (gridDim.y == 2) {
+        y = (int)(lin & 1u);
+        return (int32_t)(lin >> 1);
+    }
+    y = (int)(lin / gridDim.x);
+    return (int32_t)(lin - (unsigned)y * gridDim.x);
+}
+
 template <int SP, int LP, int RECON, int BLOCK, bool NT>
 __global__ void __launch_bounds__(BLOCK) k_wilson(WilsonArgs a) {
     using R = typename SpinorIO<SP>::R;
     __shared__ double red_lds[BLOCK / 64];
     unsigned lin = blockIdx.y * gridDim.x + blockIdx.x;
     if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x * gridDim.y);
-    const int y = (int)(lin / gridDim.x);
-    const int32_t i =
-        order_tile((int32_t)(lin - (unsigned)y * gridDim.x), (int32_t)gridDim.x, a.g.n0, a.order_c) * BLOCK +
-        threadIdx.x;
+    int y;
+    const int32_t pos = parity_slot(lin, y);
+    const int32_t i = order_tile(pos, (int32_t)gridDim.x, a.g.n0, a.order_c) * BLOCK + threadIdx.x;
     const int p = a.p0 + y;
     double red = 0.0;
     if (i < a.g.vh) {
@@ -266,11 +280,11 @@ __global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
     __shared__ double red_lds[4];
     unsigned lin = blockIdx.y * gridDim.x + blockIdx.x;
     if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x * gridDim.y);
-    const int y = (int)(lin / gridDim.x);
+    int y;
+    const int32_t pos = parity_slot(lin, y);
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int32_t i =
-        order_tile((int32_t)(lin - (unsigned)y * gridDim.x), (int32_t)gridDim.x, a.g.n0, a.order_c) * 64 + lane;
+    const int32_t i = order_tile(pos, (int32_t)gridDim.x, a.g.n0, a.order_c) * 64 + lane;
     const int p = a.p0 + y;
     const bool active = i < a.g.vh;
     if (active) {
@@ -513,8 +527,8 @@ __global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, int nrhs) {
     extern __shared__ uint32_t lw[];   // [8 dirs][link words][64 sites]
     unsigned lin = blockIdx.y * gridDim.x + blockIdx.x;
     if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x * gridDim.y);
-    const int y = (int)(lin / gridDim.x);
-    const int32_t tile = order_tile((int32_t)(lin - (unsigned)y * gridDim.x), (int32_t)gridDim.x, a.g.n0, a.order_c);
+    int y;
+    const int32_t tile = order_tile(parity_slot(lin, y), (int32_t)gridDim.x, a.g.n0, a.order_c);
     SpinorView vv[3];
     double cv[3];
     for (int j = 0; j < a.nv; ++j) {
@@ -639,9 +653,11 @@ int wilson_blocks(const ndq_geom* g, int block, int ny) {
 
 hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& args, int ny, int block,
                          hipStream_t st) {
-    // single-right-hand-side kernels keep the index order (measured faster);
-    // a.order_c stays as the caller set it (0 from wilson_args)
-    const WilsonArgs& a = args;
+    // Single-right-hand-side kernels keep the index order, except the FP64
+    // full Q, whose larger per-site footprint gains from the slice-chunked
+    // order (measured on 24^3 x 48; the F32 and F16 forms gain nothing).
+    WilsonArgs a = args;
+    if (ny == 2 && sprec == P64 && a.order_c == 0) a.order_c = tile_order(a.g, block == 0 ? 64 : block);
     const int key = sprec * 1000 + lprec * 100 + recon;
     switch (key) {
         case P64 * 1000 + P64 * 100 + 18: return launch_fmt<P64, P64, 18>(a, ny, block, st);

@@ -1,15 +1,16 @@
 """Summaries of rocprofv3 output for the stencil kernels.
 
-    python -m paper_1010_5636_amd.profiling stats   <trace_dir>  <out.txt>
-    python -m paper_1010_5636_amd.profiling traffic <fetch_dir> <write_dir> <copy_bytes> <out.json> <cmd> <block,xcd>
+    python -m paper_1010_5636_amd.profiling stats   <out.txt> <cmd> <label>=<trace_dir> ...
+    python -m paper_1010_5636_amd.profiling traffic <out.json> <copy_bytes> <cmd> <block,xcd>=<fetch_dir>,<write_dir> ...
 
 ``stats`` condenses ``*kernel_stats.csv`` (from ``rocprofv3 --kernel-trace
---stats``) into a short text table.  ``traffic`` reads the per-dispatch
-FETCH_SIZE and WRITE_SIZE counters (KiB, from two ``rocprofv3 --pmc`` runs),
-calibrates them against a plain device-to-device copy of ``copy_bytes`` bytes
-each way recorded in the same runs, and writes the HBM bytes per launch of
-every even/odd dslash instantiation, tagged with the hash of the kernel
-source and the launch shape (block, XCD remap) the runs were forced to.
+--stats``) of one or more runs into a short text table, one section per run.
+``traffic`` reads the per-dispatch FETCH_SIZE and WRITE_SIZE counters (KiB,
+from two ``rocprofv3 --pmc`` runs per launch shape), calibrates each run
+against a plain device-to-device copy of ``copy_bytes`` bytes each way
+recorded in the same run, and writes the HBM bytes per launch of every
+even/odd dslash instantiation and launch shape (block, XCD remap), tagged
+with the hash of the kernel source.
 """
 from __future__ import annotations
 
@@ -62,14 +63,16 @@ def kernel_stats(trace_dir: str):
     return rows
 
 
-def stats_text(trace_dir: str, command: str) -> str:
-    rows = sorted(kernel_stats(trace_dir), key=lambda r: -r["calls"] * r["avg_ns"])
-    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
-             f"{'format':<14}{'calls':>8}{'avg_us':>10}{'min_us':>10}{'max_us':>10}  kernel"]
-    for r in rows:
-        fmt = format_name(r["name"]) or "-"
-        lines.append(f"{fmt:<14}{r['calls']:>8}{r['avg_ns'] / 1e3:>10.3f}{r['min_ns'] / 1e3:>10.3f}"
-                     f"{r['max_ns'] / 1e3:>10.3f}  {r['name'][:110]}")
+def stats_text(runs, command: str) -> str:
+    """runs: [(label, trace_dir)]."""
+    lines = ["# rocprofv3 kernel statistics", f"# command: {command}"]
+    for label, trace_dir in runs:
+        rows = sorted(kernel_stats(trace_dir), key=lambda r: -r["calls"] * r["avg_ns"])
+        lines += ["", f"## {label}", f"{'format':<14}{'calls':>8}{'avg_us':>10}{'min_us':>10}{'max_us':>10}  kernel"]
+        for r in rows:
+            fmt = format_name(r["name"]) or "-"
+            lines.append(f"{fmt:<14}{r['calls']:>8}{r['avg_ns'] / 1e3:>10.3f}{r['min_ns'] / 1e3:>10.3f}"
+                         f"{r['max_ns'] / 1e3:>10.3f}  {r['name'][:110]}")
     return "\n".join(lines) + "\n"
 
 
@@ -96,49 +99,64 @@ def _copy_reading(vals: dict, copy_bytes: int):
     return best
 
 
-def traffic(fetch_dir: str, write_dir: str, copy_bytes: int, command: str, launch=None):
-    fetch = counters(fetch_dir, "FETCH_SIZE")
-    write = counters(write_dir, "WRITE_SIZE")
-    cf = _copy_reading(fetch, copy_bytes)
-    cw = _copy_reading(write, copy_bytes)
-    if not cf or not cw:
-        raise RuntimeError("calibration copy kernel not found in the counter output")
-    sf = copy_bytes / cf   # bytes per counter unit
-    sw = copy_bytes / cw
-    rec = {"kernel_hash": kernel_hash(), "command": command, "copy_bytes": copy_bytes,
-           "fetch_scale_bytes_per_unit": sf, "write_scale_bytes_per_unit": sw, "formats": {}}
-    for name, v in fetch.items():
-        fmt = format_name(name)
-        if fmt is None:
-            continue
-        w = write.get(name)
-        if not w:
-            continue
-        fb = sf * sorted(v)[len(v) // 2]
-        wb = sw * sorted(w)[len(w) // 2]
-        rec["formats"].setdefault(fmt, {})
-        rec["formats"][fmt].update({"kernel": name[:120], "fetch_bytes_per_launch": fb,
-                                    "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
-                                    "dispatches": len(v), "launch": launch})
+def traffic(runs, copy_bytes: int, command: str):
+    """runs: [(launch dict, fetch_dir, write_dir)].  Returns the summary with
+    one entry per (format, launch shape)."""
+    rec = {"kernel_hash": kernel_hash(), "command": command, "copy_bytes": copy_bytes, "formats": {}}
+    for launch, fetch_dir, write_dir in runs:
+        fetch = counters(fetch_dir, "FETCH_SIZE")
+        write = counters(write_dir, "WRITE_SIZE")
+        cf = _copy_reading(fetch, copy_bytes)
+        cw = _copy_reading(write, copy_bytes)
+        if not cf or not cw:
+            raise RuntimeError("calibration copy kernel not found in the counter output")
+        sf = copy_bytes / cf   # bytes per counter unit
+        sw = copy_bytes / cw
+        for name, v in fetch.items():
+            fmt = format_name(name)
+            w = write.get(name)
+            if fmt is None or not w:
+                continue
+            fb = sf * sorted(v)[len(v) // 2]
+            wb = sw * sorted(w)[len(w) // 2]
+            rec["formats"].setdefault(fmt, []).append(
+                {"launch": launch, "kernel": name[:120], "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                 "bytes_per_launch": fb + wb, "dispatches": len(v), "fetch_scale_bytes_per_unit": sf,
+                 "write_scale_bytes_per_unit": sw})
     return rec
 
 
+def lookup(rec: dict, fmt: str, launch: dict):
+    """HBM bytes per launch of format ``fmt`` at ``launch``, or None."""
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    for ent in rec.get("formats", {}).get(fmt, []):
+        if ent.get("launch") == launch:
+            return ent.get("bytes_per_launch")
+    return None
+
+
+def _launch(text: str) -> dict:
+    b, x = (int(t) for t in text.split(","))
+    return {"block": b, "xcd_remap": x}
+
+
 def main(argv):
-    if len(argv) >= 3 and argv[0] == "stats":
-        cmd = argv[3] if len(argv) > 3 else ""
-        txt = stats_text(argv[1], cmd)
-        with open(argv[2], "w") as fh:
+    if len(argv) >= 4 and argv[0] == "stats":
+        runs = [tuple(a.split("=", 1)) for a in argv[3:]]
+        txt = stats_text(runs, argv[2])
+        with open(argv[1], "w") as fh:
             fh.write(txt)
         print(txt)
         return 0
     if len(argv) >= 5 and argv[0] == "traffic":
-        cmd = argv[5] if len(argv) > 5 else ""
-        launch = None
-        if len(argv) > 6:
-            b, x = (int(t) for t in argv[6].split(","))
-            launch = {"block": b, "xcd_remap": x}
-        rec = traffic(argv[1], argv[2], int(argv[3]), cmd, launch)
-        with open(argv[4], "w") as fh:
+        runs = []
+        for a in argv[4:]:
+            launch, dirs = a.split("=", 1)
+            fd, wd = dirs.split(",", 1)
+            runs.append((_launch(launch), fd, wd))
+        rec = traffic(runs, int(argv[2]), argv[3])
+        with open(argv[1], "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec, indent=1))
         return 0
