@@ -10,7 +10,8 @@ Neuberger-Dirac operator on GPUs", Lattice 2010) defines:
   (Sec. 2.2, Eq. 5 and Eq. 6) and a Zolotarev rational approximant;
 * the low-mode projection (Sec. 2.3, Eq. 7-11) and its diagnostics;
 * the Neuberger-Dirac operator D_N and its massive form (Eq. 4, Eq. 12);
-* the su(3) link force of S = |Q psi|^2.
+* the su(3) link force of S = |Q psi|^2;
+* the index of the massless D_N by zero-mode counting (outlook of Sec. 4).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import it.  It shares no code with the GPU library
@@ -22,4 +23,4 @@ Precision: numpy float64/complex128 throughout.
 Parity status of each function is stated in its docstring; functions pinned
 only by their own invariants say "parity unpinned".
 """
-from . import geometry, dirac, approx, sign, lowmodes, overlap, force  # noqa: F401
+from . import geometry, dirac, approx, sign, lowmodes, overlap, force, index  # noqa: F401

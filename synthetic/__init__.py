@@ -147,3 +147,48 @@ def su3_directions(nsites: int, ndir: int = 8, seed: int = SEED_DIRECTIONS) -> n
 def start_vector(nsites: int, seed: int = SEED_START) -> np.ndarray:
     """Eigensolver start vector: a complex Gaussian spinor ``[V, 4, 3]``."""
     return spinor(nsites, None, seed)
+
+
+def flux_gauge_field(dims, q01: int, q23: int, noise: float = 0.0, noise_seed: int = SEED_GAUGE,
+                     gauge_seed: int | None = None) -> np.ndarray:
+    """SU(3) links carrying quantised U(1) fluxes (a smooth background of known topology).
+
+    U(1) phases with the uniform field strength 2 pi q01 / (N0 N1) on every
+    (0,1) plaquette and 2 pi q23 / (N2 N3) on every (2,3) plaquette of the
+    periodic lattice:
+
+        phi_0(x) = -2 pi q01 x1 / (N0 N1),   phi_1(x) = 2 pi q01 x0 / N0 if x1 = N1 - 1, else 0,
+        phi_2(x) = -2 pi q23 x3 / (N2 N3),   phi_3(x) = 2 pi q23 x2 / N2 if x3 = N3 - 1, else 0,
+
+    embedded as diag(e^{i phi}, e^{-i phi}, 1) (colour charges +1, -1, 0, so the
+    continuum topological charge is 2 q01 q23).  With ``noise`` > 0 every link
+    is multiplied from the left by a random SU(3) link of that width (drawn as
+    ``gauge_field(dims, noise, noise_seed)``); with ``gauge_seed`` the field is
+    then gauge transformed, U_mu(x) -> Omega(x) U_mu(x) Omega(x + mu)^H with
+    Haar-random Omega = ``haar_su3(V, gauge_seed)``.  Returns ``[V, 4, 3, 3]``.
+    """
+    dims = tuple(int(d) for d in dims)
+    n0, n1, n2, n3 = dims
+    v = volume(dims)
+    x = np.stack(np.unravel_index(np.arange(v), dims), axis=-1)
+    phi = np.zeros((v, 4))
+    phi[:, 0] = -2.0 * np.pi * q01 * x[:, 1] / (n0 * n1)
+    phi[:, 1] = np.where(x[:, 1] == n1 - 1, 2.0 * np.pi * q01 * x[:, 0] / n0, 0.0)
+    phi[:, 2] = -2.0 * np.pi * q23 * x[:, 3] / (n2 * n3)
+    phi[:, 3] = np.where(x[:, 3] == n3 - 1, 2.0 * np.pi * q23 * x[:, 2] / n2, 0.0)
+    e = np.exp(1j * phi)
+    u = np.zeros((v, 4, 3, 3), dtype=np.complex128)
+    u[..., 0, 0] = e
+    u[..., 1, 1] = e.conj()
+    u[..., 2, 2] = 1.0
+    if noise > 0.0:
+        u = np.einsum("vmab,vmbc->vmac", gauge_field(dims, noise, noise_seed), u)
+    if gauge_seed is not None:
+        om = haar_su3(v, gauge_seed)
+        u = np.einsum("vab,vmbc->vmac", om, u)
+        for mu in range(4):
+            shift = [0, 0, 0, 0]
+            shift[mu] = 1
+            nb = np.ravel_multi_index(tuple((x[:, k] + shift[k]) % dims[k] for k in range(4)), dims)
+            u[:, mu] = u[:, mu] @ om[nb].conj().transpose(0, 2, 1)
+    return np.ascontiguousarray(u)
