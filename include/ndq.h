@@ -333,6 +333,52 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
  * (row-major, interleaved complex).  The library's own small-matrix solver. */
 int ndq_host_eigh(int n, double* a, double* w, double* z);
 
+/* ---- index of the massless D_N (the workload of the outlook, Sec. 4) -------- */
+/* Zero-mode counting on D = (1 + gamma5 eps) / abar (Eq. 4 with m_q = 0), eps the
+ * approximate sign of the overlap parameters (low modes exact, Eq. 11).  On the
+ * chirality-s subspace (gamma5 psi = s psi) D^H D = (2 / abar^2) A_s with
+ * A_s = 1 + s P_s eps P_s, P_s = (1 + s gamma5) / 2, spectrum in [0, 2]; its
+ * lowest eigenpairs are found per sector by block Chebyshev-filtered subspace
+ * iteration (one sign apply per application of A_s), and the Ritz values below
+ * zero_cut are counted: n_+ and n_-, index = n_+ - n_-.  Nonzero eigenvalues of
+ * A_+ and A_- coincide, so accidental near-zero pairs cancel in the index. */
+#define NDQ_INDEX_REPORT 16
+typedef struct {
+    int32_t block;        /* vectors per sector, 2..64; must exceed the number of zero
+                             modes of either chirality (0: 8)                           */
+    int32_t degree;       /* Chebyshev filter degree per sweep (0: 8)                   */
+    int32_t max_sweeps;   /* filter sweeps per sector (0: 200)                          */
+    int32_t reserved;
+    double tol;           /* residue |A_s u - theta u| required of the Ritz pairs below the
+                             cut and of the first one above it (0: 1e-7)                 */
+    double zero_cut;      /* Ritz values theta < zero_cut count as zero modes (0: 1e-7);
+                             must exceed the approximant's error delta                   */
+} ndq_index_params;
+
+typedef struct {
+    int32_t n_plus, n_minus;   /* zero modes of chirality +1 and -1                      */
+    int32_t index;             /* n_plus - n_minus                                        */
+    int32_t block;             /* block size used                                         */
+    int32_t sweeps[2];         /* filter sweeps, sector + then -                          */
+    int32_t converged[2];
+    double theta[2][NDQ_INDEX_REPORT];   /* lowest Ritz values of A_+ and A_-, ascending */
+    double resid[2][NDQ_INDEX_REPORT];   /* their residues                               */
+    int64_t sign_applies;
+    double seconds;
+} ndq_index_info;
+
+size_t ndq_index_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p, const ndq_index_params* params);
+
+/*   U: FP64 links;  p: overlap parameters (approximant, lam_max, Wilson mass m, optional
+ *   exact low modes of Q; mq is not used);  params: NULL for the defaults;
+ *   start: one nonzero FP64 NDQ_FULL field (the block start vectors are phase-
+ *   randomised, chirally projected copies);  info: out (filled also on error).
+ *   Synchronises `stream`.  Errors: NDQ_EINVAL, NDQ_EPREC, NDQ_ENOMEM (workspace),
+ *   NDQ_ENOCONV (sweep limit, or every converged Ritz value of a sector below the
+ *   cut: the block is too small), NDQ_ENAN (the block lost rank). */
+int ndq_index_DN(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p, const ndq_index_params* params,
+                 const ndq_spinor* start, ndq_index_info* info, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- derivatives (not in the paper; follow from Eq. 1) --------------------- */
 /* For y = Q[U] psi and a cotangent g (dL = Re<g, dy>): the su(3) link force
  *   F^a_mu(x) = dL/dw for U_mu(x) -> exp(i w T_a) U_mu(x),  T_a = lambda_a / 2,

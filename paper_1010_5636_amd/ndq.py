@@ -86,6 +86,29 @@ class _LmInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class _IndexParams(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("degree", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tol", ctypes.c_double), ("zero_cut", ctypes.c_double)]
+
+
+INDEX_REPORT = 16
+
+
+class _IndexInfo(ctypes.Structure):
+    _fields_ = [("n_plus", ctypes.c_int32), ("n_minus", ctypes.c_int32), ("index", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("sweeps", ctypes.c_int32 * 2), ("converged", ctypes.c_int32 * 2),
+                ("theta", (ctypes.c_double * INDEX_REPORT) * 2), ("resid", (ctypes.c_double * INDEX_REPORT) * 2),
+                ("sign_applies", ctypes.c_int64), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        n = min(self.block, INDEX_REPORT)
+        return {"n_plus": self.n_plus, "n_minus": self.n_minus, "index": self.index, "block": self.block,
+                "sweeps": list(self.sweeps), "converged": [bool(c) for c in self.converged],
+                "theta_plus": list(self.theta[0])[:n], "theta_minus": list(self.theta[1])[:n],
+                "resid_plus": list(self.resid[0])[:n], "resid_minus": list(self.resid[1])[:n],
+                "sign_applies": self.sign_applies, "seconds": self.seconds}
+
+
 class _SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("inner_prec", ctypes.c_int32)]
@@ -134,6 +157,9 @@ _SIG = {
                                   ctypes.POINTER(_Spinor), _P, ctypes.POINTER(_D), ctypes.POINTER(_D),
                                   ctypes.POINTER(_LmInfo), _P, ctypes.c_size_t, _P]),
     "ndq_host_eigh": (_I, [_I, _P, _P, _P]),
+    "ndq_index_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(_Params), ctypes.POINTER(_IndexParams)]),
+    "ndq_index_DN": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Params), ctypes.POINTER(_IndexParams),
+                          ctypes.POINTER(_Spinor), ctypes.POINTER(_IndexInfo), _P, ctypes.c_size_t, _P]),
     "ndq_solve_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(_Params), ctypes.POINTER(_Params),
                                                     ctypes.POINTER(_SolveParams)]),
     "ndq_solve_DN": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Gauge), ctypes.POINTER(_Params),
@@ -458,6 +484,27 @@ def lowmodes_compute(geom: Geometry, U: GaugeField, m: float, lam_max: float, st
                                     _ptr(ws), nbytes, _stream(stream))
     _check(rc)
     return modes, nu, rho, info.as_dict()
+
+
+def index_DN(geom: Geometry, U: GaugeField, ov: Overlap, start: SpinorField, block: int = 8, degree: int = 8,
+             max_sweeps: int = 200, tol: float = 1e-7, zero_cut: float = 1e-7, stream=None) -> dict:
+    """Index of the massless D_N by zero-mode counting (ndq_index_DN): returns
+    {n_plus, n_minus, index, lowest Ritz values and residues per sector, ...}.
+    On an error the raised NdqError carries the same dict as ``.info``."""
+    p = _IndexParams(int(block), int(degree), int(max_sweeps), 0, float(tol), float(zero_cut))
+    nbytes = int(lib().ndq_index_workspace_bytes(geom.handle, ctypes.byref(ov.p), ctypes.byref(p)))
+    if nbytes == 0:
+        raise NdqError(-1, "bad index parameters")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    info = _IndexInfo()
+    rc = lib().ndq_index_DN(geom.handle, ctypes.byref(U.desc), ctypes.byref(ov.p), ctypes.byref(p),
+                            ctypes.byref(start.desc), ctypes.byref(info), _ptr(ws), nbytes, _stream(stream))
+    try:
+        _check(rc)
+    except NdqError as e:
+        e.info = info.as_dict()
+        raise
+    return info.as_dict()
 
 
 def host_eigh(a):

@@ -151,3 +151,27 @@ def test_minmax_library_at_rounding_floor(ndq):
     ref = approx.minimax_polynomial(k * k, n)
     assert a.delta < 1e-13
     assert np.abs(c - ref.c).max() < 1e-12
+
+
+def test_index_validation_before_launch(ndq):
+    """ndq_index_DN rejects bad parameters, precisions and workspaces on the host."""
+    lib = ndq.lib()
+    g = ndq.Geometry((4, 4, 4, 4))
+    fake = 0x1000  # never dereferenced: validation fails first
+    a = ndq.Approx(ndq.ZOLOTAREV, 0.09, 8)
+    p = ndq._Params(-1.4, 0.0, 6.6, a.handle.value, None, None, 0, 0, 1e-12, 1000, 8, 0)
+    U = ndq._Gauge(fake, ndq.F64, 18)
+    start = ndq._Spinor(fake, ndq.F64, ndq.FULL, 1)
+    info = ndq._IndexInfo()
+    by = ctypes.byref
+    bad = ndq._IndexParams(65, 8, 10, 0, 1e-7, 1e-7)
+    assert lib.ndq_index_workspace_bytes(g.handle, by(p), by(bad)) == 0
+    assert lib.ndq_index_DN(g.handle, by(U), by(p), by(bad), by(start), by(info), None, 0, None) == -1
+    ok = ndq._IndexParams(0, 0, 0, 0, 0.0, 0.0)
+    need = lib.ndq_index_workspace_bytes(g.handle, by(p), by(ok))
+    assert need > 3 * 8 * 256 * 192       # three blocks of the default 8 vectors
+    start32 = ndq._Spinor(fake, ndq.F32, ndq.FULL, 1)
+    assert lib.ndq_index_DN(g.handle, by(U), by(p), by(ok), by(start32), by(info), None, 0, None) == -3
+    assert lib.ndq_index_DN(g.handle, by(U), by(p), by(ok), by(start), by(info), None, 0, None) == -4
+    assert "workspace" in lib.ndq_last_error().decode()
+    assert info.block == 0 and info.index == 0
