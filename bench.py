@@ -377,6 +377,49 @@ def graph_leg(log):
     return out
 
 
+INDEX_DIMS = (32, 16, 16, 16)
+
+
+def index_leg(log):
+    """Index of the massless D_N by zero-mode counting (ndq_index_DN) on a
+    16^3 x 32 background with quantised fluxes (q01, q23) = (1, 1) in the
+    diag(e^{i phi}, e^{-i phi}, 1) embedding (topological charge 2), light noise
+    (width 0.2) and a random gauge transformation; FP64 sign (minimax
+    polynomial, delta <= 1e-10, 4 exact low modes).  Expected index: -2."""
+    import torch
+    import synthetic
+    import paper_1010_5636_amd as ndq
+    dev = torch.device("cuda")
+    t0 = time.perf_counter()
+    g = ndq.Geometry(INDEX_DIMS)
+    u = synthetic.flux_gauge_field(INDEX_DIMS, 1, 1, noise=0.2, gauge_seed=synthetic.SEED_HAAR)
+    U = ndq.GaugeField.pack(g, torch.from_numpy(u).to(dev), ndq.F64, 18)
+    del u
+    start = ndq.SpinorField.pack(g, torch.from_numpy(synthetic.start_vector(g.volume)).to(dev), ndq.F64, ndq.FULL)
+    modes, nu, _, lm = ndq.lowmodes_compute(g, U, M, LAM_MAX, start, 4, tol=1e-10)
+    t_modes = time.perf_counter() - t0
+    ap = poly_for(ndq, ((lm["lam_next"] - lm["rho_next"]) / LAM_MAX) ** 2, 1e-10)
+    ov = ndq.Overlap(g, M, ap, LAM_MAX, modes=modes, nu=nu)
+    torch.cuda.synchronize()
+    r = ndq.index_DN(g, U, ov, start, block=8, zero_cut=1e-7)
+    # one sign apply alone, for the cost per application
+    x = start.like()
+    y = start.like()
+    x.buf.copy_(start.buf)
+    ndq.apply_sign(g, U, ov, x, y)
+    ms_sign = _time_events(lambda: ndq.apply_sign(g, U, ov, x, y), 5)
+    out = {"workload": "index of the massless D_N, 16^3x32 flux background (q01 = q23 = 1, noise 0.2, gauge "
+                       "transformed), FP64 polynomial sign (degree %d, delta %.1e), 4 exact low modes" % (ap.n, ap.delta),
+           "n_plus": r["n_plus"], "n_minus": r["n_minus"], "index": r["index"], "index_expected": -2,
+           "block": r["block"], "sweeps": r["sweeps"], "filter_degree": r["degree"], "sign_applies": r["sign_applies"],
+           "seconds": round(r["seconds"], 3), "sign_ms": round(ms_sign, 3),
+           "first_nonzero_theta": [r["theta_plus"][r["n_plus"]], r["theta_minus"][r["n_minus"]]],
+           "setup_lowmodes_s": round(t_modes, 2)}
+    log(f"index leg: index {r['index']} (n+ {r['n_plus']}, n- {r['n_minus']}), {r['sign_applies']} sign applies, "
+        f"{r['seconds']:.1f} s")
+    return out
+
+
 def autograd_leg(log):
     """S = psi^H Q^2 psi on 16^3 x 32 in FP64 through the torch autograd function
     (forward Q, backward Q and the su(3) force kernel, canonical tensors in and
@@ -621,6 +664,7 @@ def main():
         out["batching"] = batch_leg(log)
         out["graph_multishift"] = graph_leg(log)
         out["autograd"] = autograd_leg(log)
+        out["index"] = index_leg(log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

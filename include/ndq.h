@@ -346,11 +346,14 @@ int ndq_host_eigh(int n, double* a, double* w, double* z);
 typedef struct {
     int32_t block;        /* vectors per sector, 2..64; must exceed the number of zero
                              modes of either chirality (0: 8)                           */
-    int32_t degree;       /* Chebyshev filter degree per sweep (0: 8)                   */
+    int32_t degree;       /* Chebyshev filter degree per sweep (0: adaptive, the degree that
+                             amplifies the null space ~1e4-fold over [a, 2] per sweep, <= 200) */
     int32_t max_sweeps;   /* filter sweeps per sector (0: 200)                          */
     int32_t reserved;
     double tol;           /* residue |A_s u - theta u| required of the Ritz pairs below the
-                             cut and of the first one above it (0: 1e-7)                 */
+                             cut (0: 1e-7); the first pair above the cut must satisfy
+                             theta - residue > zero_cut, and the null space must have been
+                             amplified 1e12-fold by the filter sweeps                    */
     double zero_cut;      /* Ritz values theta < zero_cut count as zero modes (0: 1e-7);
                              must exceed the approximant's error delta                   */
 } ndq_index_params;
@@ -361,6 +364,7 @@ typedef struct {
     int32_t block;             /* block size used                                         */
     int32_t sweeps[2];         /* filter sweeps, sector + then -                          */
     int32_t converged[2];
+    int32_t degree[2];         /* filter degree of the last sweep                         */
     double theta[2][NDQ_INDEX_REPORT];   /* lowest Ritz values of A_+ and A_-, ascending */
     double resid[2][NDQ_INDEX_REPORT];   /* their residues                               */
     int64_t sign_applies;

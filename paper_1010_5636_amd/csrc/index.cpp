@@ -10,11 +10,13 @@
 // A_s, whose spectrum lies in [0, 2].  The lowest eigenpairs of A_s are found
 // in each sector by block Chebyshev-filtered subspace iteration (Zhou & Saad):
 // a block of nb chiral vectors is filtered by T_d of A_s mapped from
-// [a, 2 + margin] onto [-1, 1] (a = the block's largest Ritz value),
+// [a, 2 + margin] onto [-1, 1] (a = the block's largest Ritz value; d chosen
+// so that one sweep amplifies the null space about 1e4-fold over [a, 2]),
 // orthonormalised (Gram matrix on the matrix cores, applied twice) and rotated
-// onto the Ritz vectors of A_s.  Once the Ritz pairs below the cut and the
-// first one above it have residues <= tol, the pairs below the cut are
-// counted: n_s.  The index is n_+ - n_-.  One application of A_s is one sign
+// onto the Ritz vectors of A_s.  Once the null space has been amplified
+// 1e12-fold in total, the Ritz pairs below the cut have residues <= tol and
+// the first pair above the cut lies clearly above it, the pairs below the
+// cut are counted: n_s.  The index is n_+ - n_-.  One application of A_s is one sign
 // apply; everything else is BLAS on FP64 fields.
 #include <math.h>
 #include <string.h>
@@ -151,8 +153,29 @@ struct Sector {
     std::vector<double> theta, resid;
     int sweeps = 0;
     int count = 0;
+    int degree = 0;          // filter degree of the last sweep
+    double log_amp = 0.0;    // log of the null space's total amplification over [a, 2]
     bool converged = false;
 };
+
+// Filter degree that amplifies the null space by about kAmplify over the
+// damped interval [a, b] in one sweep: |T_d(A~(0))| = cosh(d acosh((a + b) / (b - a))).
+constexpr double kAmplify = 1e4;
+constexpr int kMaxDegree = 200;
+// Total amplification of the null space before a count is accepted: a null
+// vector's weight in a random start vector is about dim^{-1/2} (>= 1e-4 for
+// the lattices here), so after 1e12 it dominates every other direction by
+// about 1e8 and cannot be missing from a block that still has room.
+constexpr double kMinAmplification = 1e12;
+double log_amplification(double a, double b, int d) {
+    const double t = d * acosh((a + b) / (b - a));
+    return t + log1p(exp(-2.0 * t)) - log(2.0);   // log cosh t
+}
+int adaptive_degree(double a, double b) {
+    const double x = (a + b) / (b - a);
+    const double d = ceil(acosh(kAmplify) / acosh(x));
+    return (int)std::min<double>(std::max(d, 4.0), kMaxDegree);
+}
 
 // Rayleigh-Ritz of A_s in span(X) (orthonormal, nb vectors): W = A_s X into
 // free1, M = X^H W, the Ritz vectors X Z into free2 and A_s X Z into X's
@@ -201,12 +224,15 @@ int run_sector(IxCtx& c, int s, const ndq_spinor* start, char* B0, char* B1, cha
     if ((rc = rayleigh_ritz(c, s, X, F1, F2, nb, sec))) return rc;
     const double up = 2.0 + kUpperMargin;
     for (sec.sweeps = 0;; ++sec.sweeps) {
-        // pairs below the cut and the first one above it must have converged
+        // Accept the count once the null space has been amplified enough that
+        // no zero mode can be missing from the block, the pairs below the cut
+        // have converged, and the first pair above it lies clearly above the
+        // cut (an eigenvalue within its residue of theta).
         int below = 0;
         while (below < nb - 1 && sec.theta[below] < ip.zero_cut) ++below;
-        const int need = std::min(below + 1, nb - 1);
-        bool ok = true;
-        for (int j = 0; j < need; ++j) ok = ok && sec.resid[j] <= ip.tol;
+        bool ok = sec.log_amp >= log(kMinAmplification);
+        for (int j = 0; j < below; ++j) ok = ok && sec.resid[j] <= ip.tol;
+        if (below < nb - 1) ok = ok && sec.theta[below] - sec.resid[below] > ip.zero_cut;
         sec.count = below;
         if (ok) {
             if (below >= nb - 1)
@@ -216,10 +242,13 @@ int run_sector(IxCtx& c, int s, const ndq_spinor* start, char* B0, char* B1, cha
             return NDQ_OK;
         }
         if (sec.sweeps >= ip.max_sweeps)
-            return fail(NDQ_ENOCONV, "index: chirality %+d not converged after %d sweeps (residue %g of %g)", s,
-                        sec.sweeps, sec.resid[need - 1], ip.tol);
+            return fail(NDQ_ENOCONV, "index: chirality %+d not converged after %d sweeps (largest residue below "
+                        "the cut %g, tol %g)", s, sec.sweeps,
+                        below ? *std::max_element(sec.resid.begin(), sec.resid.begin() + below) : 0.0, ip.tol);
         const double a = std::min(std::max(sec.theta[nb - 1], kCutoffFloor), 1.9);
-        if ((rc = filter(c, s, X, F1, nb, a, up, ip.degree))) return rc;
+        sec.degree = ip.degree > 0 ? ip.degree : adaptive_degree(a, up);
+        if ((rc = filter(c, s, X, F1, nb, a, up, sec.degree))) return rc;
+        sec.log_amp += log_amplification(a, up, sec.degree);
         // two passes: the filtered block can be ill-conditioned
         if ((rc = orthonormalise(c, F1, X, nb))) return rc;
         if ((rc = orthonormalise(c, X, F1, nb))) return rc;
@@ -232,7 +261,6 @@ void with_defaults(const ndq_index_params* in, ndq_index_params& ip) {
     memset(&ip, 0, sizeof(ip));
     if (in) ip = *in;
     if (ip.block == 0) ip.block = 8;
-    if (ip.degree == 0) ip.degree = 8;
     if (ip.max_sweeps == 0) ip.max_sweeps = 200;
     if (ip.tol == 0.0) ip.tol = 1e-7;
     if (ip.zero_cut == 0.0) ip.zero_cut = 1e-7;
@@ -276,7 +304,7 @@ int ndq_index_DN(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params
     ndq_index_params ip;
     with_defaults(params, ip);
     if (ip.block < 2 || ip.block > 64) return fail(NDQ_EINVAL, "index: block must be in [2, 64]");
-    if (ip.degree < 1 || ip.degree > 1000) return fail(NDQ_EINVAL, "index: degree must be in [1, 1000]");
+    if (ip.degree < 0 || ip.degree > 1000) return fail(NDQ_EINVAL, "index: degree must be in [0, 1000]");
     if (ip.max_sweeps < 1) return fail(NDQ_EINVAL, "index: max_sweeps must be positive");
     if (!(ip.tol > 0) || !(ip.zero_cut > 0)) return fail(NDQ_EINVAL, "index: tol and zero_cut must be positive");
     int rc = check_gauge(U);
@@ -320,6 +348,7 @@ int ndq_index_DN(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params
             info->resid[k][j] = sec[k].resid[j];
         }
         info->sweeps[k] = sec[k].sweeps;
+        info->degree[k] = sec[k].degree;
         info->converged[k] = sec[k].converged ? 1 : 0;
     }
     info->n_plus = sec[0].count;

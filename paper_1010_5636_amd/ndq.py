@@ -97,6 +97,7 @@ INDEX_REPORT = 16
 class _IndexInfo(ctypes.Structure):
     _fields_ = [("n_plus", ctypes.c_int32), ("n_minus", ctypes.c_int32), ("index", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("sweeps", ctypes.c_int32 * 2), ("converged", ctypes.c_int32 * 2),
+                ("degree", ctypes.c_int32 * 2),
                 ("theta", (ctypes.c_double * INDEX_REPORT) * 2), ("resid", (ctypes.c_double * INDEX_REPORT) * 2),
                 ("sign_applies", ctypes.c_int64), ("seconds", ctypes.c_double)]
 
@@ -104,6 +105,7 @@ class _IndexInfo(ctypes.Structure):
         n = min(self.block, INDEX_REPORT)
         return {"n_plus": self.n_plus, "n_minus": self.n_minus, "index": self.index, "block": self.block,
                 "sweeps": list(self.sweeps), "converged": [bool(c) for c in self.converged],
+                "degree": list(self.degree),
                 "theta_plus": list(self.theta[0])[:n], "theta_minus": list(self.theta[1])[:n],
                 "resid_plus": list(self.resid[0])[:n], "resid_minus": list(self.resid[1])[:n],
                 "sign_applies": self.sign_applies, "seconds": self.seconds}
@@ -486,7 +488,7 @@ def lowmodes_compute(geom: Geometry, U: GaugeField, m: float, lam_max: float, st
     return modes, nu, rho, info.as_dict()
 
 
-def index_DN(geom: Geometry, U: GaugeField, ov: Overlap, start: SpinorField, block: int = 8, degree: int = 8,
+def index_DN(geom: Geometry, U: GaugeField, ov: Overlap, start: SpinorField, block: int = 8, degree: int = 0,
              max_sweeps: int = 200, tol: float = 1e-7, zero_cut: float = 1e-7, stream=None) -> dict:
     """Index of the massless D_N by zero-mode counting (ndq_index_DN): returns
     {n_plus, n_minus, index, lowest Ritz values and residues per sector, ...}.

@@ -69,9 +69,15 @@ def check_against_oracle(r, spectra, nb):
     assert (r["n_plus"], r["n_minus"], r["index"]) == (want["n_plus"], want["n_minus"], want["index"])
     for s, key in ((1, "plus"), (-1, "minus")):
         theta, res, ev = np.array(r["theta_" + key]), np.array(r["resid_" + key]), spectra[s]
-        n = r["n_" + key] + 1       # the pairs below the cut and the first one above it
+        n = r["n_" + key]
+        # the pairs below the cut: converged, on the oracle's lowest eigenvalues
         assert (res[:n] <= 1e-7).all()
         assert np.all(np.abs(theta[:n] - ev[:n]) <= 2 * res[:n] + 1e-12), (key, theta[:n], ev[:n])
+        # the first pair above the cut: above the cut, an upper bound of the
+        # n-th eigenvalue, within its residue of some eigenvalue
+        assert theta[n] - res[n] > CUT
+        assert theta[n] >= ev[n] - 1e-12
+        assert np.abs(ev - theta[n]).min() <= res[n] + 1e-12
 
 
 def test_flux_background_vs_oracle(flux):
