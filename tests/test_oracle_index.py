@@ -114,3 +114,24 @@ def test_sector_operator_is_DdagD(flux_pp):
     for s in (1, -1):
         idx = np.flatnonzero(chi == s)
         assert np.abs(dd[np.ix_(idx, idx)] - 2.0 / abar ** 2 * index.sector_operator(c.eps, s)).max() < 1e-12
+
+
+@pytest.mark.slow
+def test_massive_normal_operator_on_sectors(flux_pp):
+    """The chirality-sector form of the massive normal equations used by the
+    sector solver: with D^m = alpha + beta gamma5 eps (Eq. 4 with the massive
+    form of Eq. 12: alpha = 1/abar + mq/2, beta = 1/abar - mq/2), on the
+    chirality-s subspace (D^m)^H D^m = (alpha - beta)^2 + 2 alpha beta A_s, and
+    it maps each sector to itself (zero off-diagonal blocks)."""
+    c = flux_pp
+    mq = 0.05
+    abar = overlap.abar(S)
+    alpha, beta = 1.0 / abar + mq / 2, 1.0 / abar - mq / 2
+    d = overlap.dense_DN(c.eps, S, mq)
+    dd = d.conj().T @ d
+    chi = index.chirality(V)
+    ip, im = np.flatnonzero(chi == 1), np.flatnonzero(chi == -1)
+    assert np.abs(dd[np.ix_(ip, im)]).max() < 1e-12
+    for s, idx in ((1, ip), (-1, im)):
+        want = (alpha - beta) ** 2 * np.eye(idx.size) + 2 * alpha * beta * index.sector_operator(c.eps, s)
+        assert np.abs(dd[np.ix_(idx, idx)] - want).max() < 1e-12
