@@ -159,19 +159,32 @@ def solve_leg(log):
            "approximant": {"kind": "minimax polynomial (Clenshaw)", "eps": eps, "degree_fp64": ap64.n,
                            "delta_fp64": ap64.delta, "degree_inner": ap_lo.n, "delta_inner": ap_lo.delta}}
     runs = {}
-    for name, prec, Ulo, ovlo, itol in (("mixed_f32", ndq.F32, U32, ov_lo, 0.0),
-                                        ("mixed_f16", ndq.F16, U16, ov_lo, 2e-3),
-                                        ("fp64", ndq.F64, None, None, 0.0)):
+    # a spin-colour point source (spin 2, colour 0 at site 0): chiral, so the
+    # chirality-sector inner solver needs one sector
+    point = torch.zeros((v, 4, 3), dtype=torch.complex128, device=dev)
+    point[0, 2, 0] = 1.0
+    b_point = ndq.SpinorField.pack(g, point, ndq.F64, ndq.FULL)
+    del point
+    for name, prec, Ulo, ovlo, itol, sectors, rhs in (
+            ("mixed_f32", ndq.F32, U32, ov_lo, 0.0, False, b),
+            ("mixed_f16", ndq.F16, U16, ov_lo, 2e-3, False, b),
+            ("fp64", ndq.F64, None, None, 0.0, False, b),
+            ("point_mixed_f32", ndq.F32, U32, ov_lo, 0.0, False, b_point),
+            ("point_mixed_f32_sectors", ndq.F32, U32, ov_lo, 0.0, True, b_point),
+            ("point_fp64", ndq.F64, None, None, 0.0, False, b_point),
+            ("point_fp64_sectors", ndq.F64, None, None, 0.0, True, b_point)):
         x = ndq.SpinorField(g, ndq.F64, ndq.FULL)
         x.buf.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = ndq.solve_DN(g, U64, ov64, b, x, tol=1e-10, U_lo=Ulo, ov_lo=ovlo, inner_prec=prec, inner_tol=itol,
-                          max_outer=30)
+        st = ndq.solve_DN(g, U64, ov64, rhs, x, tol=1e-10, U_lo=Ulo, ov_lo=ovlo, inner_prec=prec, inner_tol=itol,
+                          max_outer=30, sectors=sectors)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         runs[name] = {"seconds": round(el, 3), "solves_per_s": round(1.0 / el, 4), "residual": st["residual"],
-                      "outer": st["outer"], "inner_cg_iterations": st["inner"], "q_applies": st["q_applies"]}
+                      "outer": st["outer"], "inner_cg_iterations": st["inner"], "q_applies": st["q_applies"],
+                      "inner_solver": "chirality sectors" if sectors else "CGNE",
+                      "source": "point (chiral)" if rhs is b_point else "complex Gaussian"}
         log(f"solve leg: {name} {el:.2f} s, residual {st['residual']:.2e}, outer {st['outer']}, "
             f"inner {st['inner']}, Q applies {st['q_applies']}")
         del x
@@ -180,7 +193,7 @@ def solve_leg(log):
     # inner precision for the mixed runs (the FP64 outer applies are ~2% of them)
     qbytes = {"mixed_f32": 384, "mixed_f16": 200, "fp64": 960}
     for name, r in runs.items():
-        rb = r["q_applies"] * qbytes[name] * v
+        rb = r["q_applies"] * qbytes["mixed_f32" if "f32" in name else "fp64" if "fp64" in name else name] * v
         r["q_alg_bytes"] = rb
         r["q_roofline_s"] = round(rb / (HBM_PEAK_GBS * 1e9), 4)
         r["frac_of_roofline"] = round(rb / (HBM_PEAK_GBS * 1e9) / r["seconds"], 4)
@@ -205,6 +218,9 @@ def solve_leg(log):
     out["runs"] = runs
     out["speedup_mixed_f32_vs_fp64"] = round(runs["fp64"]["seconds"] / runs["mixed_f32"]["seconds"], 3)
     out["speedup_mixed_f16_vs_fp64"] = round(runs["fp64"]["seconds"] / runs["mixed_f16"]["seconds"], 3)
+    out["speedup_sectors_vs_cgne_point_source"] = {
+        "mixed_f32": round(runs["point_mixed_f32"]["seconds"] / runs["point_mixed_f32_sectors"]["seconds"], 3),
+        "fp64": round(runs["point_fp64"]["seconds"] / runs["point_fp64_sectors"]["seconds"], 3)}
     return out
 
 

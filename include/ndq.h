@@ -248,6 +248,10 @@ typedef struct {
     int32_t max_inner;    /* CG iterations per inner solve (<= 0: no limit)                 */
     double inner_tol;     /* inner relative residual (<= 0: 1e-5 mixed, tol/2 plain FP64)   */
     int32_t inner_prec;   /* NDQ_F64: plain FP64 solve; NDQ_F32 / NDQ_F16: mixed precision  */
+    int32_t sectors;      /* inner solver: 0 = CGNE on D^H D (two sign applies per iteration);
+                             1 = CG on each chirality sector of D^H D, which commutes with
+                             gamma5 (one sign apply per iteration; a chiral source, e.g. a
+                             point source, needs one sector)                                 */
 } ndq_solve_params;
 
 size_t ndq_solve_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p64, const ndq_overlap_params* plo,
@@ -255,8 +259,8 @@ size_t ndq_solve_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p6
 
 /* x = (D_N^m)^{-1} b (Eq. 4 with the massive form of Eq. 12).  FP64 defect
  * correction: r = b - D x with the FP64 operator (U64, p64); while |r| > tol |b|,
- * solve D e = r/|r| by CG on the normal equations (D^H = gamma5 D gamma5) in the
- * inner precision (U_lo and p_lo: F32 arithmetic on F32 or F16 storage, with their
+ * solve D e = r/|r| by CG on the normal equations (D^H = gamma5 D gamma5), or by
+ * CG on their chirality sectors (sp->sectors), in the inner precision (U_lo and p_lo: F32 arithmetic on F32 or F16 storage, with their
  * own approximant; or FP64 with U64, p64 for the plain solve) and set x += |r| e.
  * b, x: F64 NDQ_FULL, nrhs 1; x holds the initial guess on entry.  Synchronises
  * `stream`.  stats: outer steps, inner CG iterations, Q applications, final true

@@ -9,6 +9,18 @@
 // step plus the final true-residual check); with F32 (or F16 storage) the
 // inner solves run in FP32 arithmetic on cheaper fields and approximant, and
 // the FP64 outer steps restore the full accuracy.
+//
+// Alternative inner solver (sectors = 1): D = alpha + beta gamma5 eps, so D^H D
+// commutes with gamma5 and on the chirality-s subspace equals
+//     H_s = (alpha - beta)^2 + 2 alpha beta (1 + s P_s eps P_s)
+// (with eps^2 = 1).  Then e = D^{-1} r = D^H (D^H D)^{-1} r =
+// D^H (H_+^{-1} P_+ r + H_-^{-1} P_- r): one CG per chirality sector with one
+// sign apply per iteration in the inner precision, and D^H applied with the
+// FP64 operator.  A chiral source (a spin-colour point source in the chiral
+// basis) needs only its own sector: half the sign applies of CGNE per
+// iteration.  The normal equations square the condition number, so the inner
+// operator's error reaches y amplified by ~1/mq^2 (CGNE: ~1/mq); mixed-precision
+// sector solves therefore gain less per outer step than CGNE.
 #include <math.h>
 #include <string.h>
 
@@ -31,14 +43,20 @@ struct DOp {
     ndq_spinor S;         // sign(Q) in
 };
 
-// out = D_N^m in (gamma5 on the input and/or output when herm)
-int d_apply(DOp& d, const ndq_spinor* in, const ndq_spinor* out) {
+// d.S = sign(Q) in (the approximant of d.p, low modes exact)
+int sign_apply(DOp& d, const ndq_spinor* in) {
     d.ar->used = d.mark;
     d.ar->overflow = false;
     ndq_stats s;
     memset(&s, 0, sizeof(s));
     int rc = apply_sign(d.g, d.U, d.p, in, &d.S, *d.ar, &s, d.st);
     d.stats->q_applies += s.q_applies;
+    return rc;
+}
+
+// out = D_N^m in
+int d_apply(DOp& d, const ndq_spinor* in, const ndq_spinor* out) {
+    int rc = sign_apply(d, in);
     if (rc) return rc;
     const double inv_abar = -d.p->m;
     const ndq_spinor* v[2] = {in, &d.S};
@@ -130,6 +148,128 @@ int cgne(DOp& d, const ndq_spinor* rhs, Vecs& v, double tol, int max_iter, doubl
     return NDQ_OK;
 }
 
+// Coefficients of D = alpha + beta gamma5 eps: alpha = 1/abar + mq/2, beta = 1/abar - mq/2.
+double d_alpha(const DOp& d) { return -d.p->m + 0.5 * d.p->mq; }
+double d_beta(const DOp& d) { return -d.p->m - 0.5 * d.p->mq; }
+
+// out = H_s in = (alpha^2 + beta^2) in + 2 s alpha beta P_s eps in, for a chirality-s `in`
+// (2 s alpha beta P_s S = s alpha beta S + alpha beta gamma5 S).
+int h_apply(DOp& d, int s, const ndq_spinor* in, const ndq_spinor* out) {
+    int rc = sign_apply(d, in);
+    if (rc) return rc;
+    const double a = d_alpha(d), b = d_beta(d);
+    const ndq_spinor* v[3] = {in, &d.S, &d.S};
+    const Coef c[3] = {hc(a * a + b * b), hc(s * a * b), hc(a * b)};
+    const int g5[3] = {0, 0, 1};
+    return lincomb(d.g, d.prec, out, 3, v, c, g5, nullptr, d.st);
+}
+
+int host_dot_re(const ndq_geom* g, const ndq_spinor* x, const ndq_spinor* y, double* partials, double* dscal,
+                double* out, hipStream_t st) {
+    int rc = dot(g, x, y, partials, dscal, st);
+    if (rc) return rc;
+    double z[2];
+    NDQ_HIP(hipMemcpyAsync(z, dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    NDQ_HIP(hipStreamSynchronize(st));
+    if (!isfinite(z[0])) return fail(NDQ_ENAN, "solve: NaN or Inf in a dot product");
+    *out = z[0];
+    return NDQ_OK;
+}
+
+// y = H_s^{-1} rhs by CG (rhs of chirality s; y starts at zero); r, p, w work vectors.
+int sector_cg(DOp& d, int s, const ndq_spinor* rhs, const ndq_spinor* y, const ndq_spinor* r, const ndq_spinor* p,
+              const ndq_spinor* w, double tol, int max_iter, double* partials, double* dscal, int* iters) {
+    const ndq_geom* g = d.g;
+    hipStream_t st = d.st;
+    int rc;
+    if ((rc = lincomb(g, d.prec, y, 0, nullptr, nullptr, nullptr, nullptr, st))) return rc;
+    const ndq_spinor* src[2] = {rhs, nullptr};
+    Coef cf[2] = {hc(1.0), hc(0.0)};
+    if ((rc = lincomb(g, d.prec, r, 1, src, cf, nullptr, nullptr, st))) return rc;
+    if ((rc = lincomb(g, d.prec, p, 1, src, cf, nullptr, nullptr, st))) return rc;
+    double rr;
+    if ((rc = host_norm2(g, r, partials, dscal, &rr, st))) return rc;
+    const double r0 = rr;
+    int it = 0;
+    while (it < max_iter && rr > tol * tol * r0) {
+        if ((rc = h_apply(d, s, p, w))) return rc;
+        double pw;
+        if ((rc = host_dot_re(g, p, w, partials, dscal, &pw, st))) return rc;
+        if (!(pw > 0)) return fail(NDQ_ENAN, "solve: sector operator not positive (p^H H p = %g)", pw);
+        const double alpha = rr / pw;
+        src[0] = y;
+        src[1] = p;
+        cf[0] = hc(1.0);
+        cf[1] = hc(alpha);
+        if ((rc = lincomb(g, d.prec, y, 2, src, cf, nullptr, nullptr, st))) return rc;
+        src[0] = r;
+        src[1] = w;
+        cf[1] = hc(-alpha);
+        if ((rc = lincomb(g, d.prec, r, 2, src, cf, nullptr, nullptr, st))) return rc;
+        double rr_new;
+        if ((rc = host_norm2(g, r, partials, dscal, &rr_new, st))) return rc;
+        ++it;
+        if (rr_new <= tol * tol * r0) break;
+        const double beta = rr_new / rr;
+        rr = rr_new;
+        src[0] = r;
+        src[1] = p;
+        cf[0] = hc(1.0);
+        cf[1] = hc(beta);
+        if ((rc = lincomb(g, d.prec, p, 2, src, cf, nullptr, nullptr, st))) return rc;
+    }
+    *iters = it;
+    return NDQ_OK;
+}
+
+// y = (D^H D)^{-1} rhs = H_+^{-1} P_+ rhs + H_-^{-1} P_- rhs into v.t, by the
+// two chirality sectors (|rhs| = 1 on entry); the caller forms e = D^H y.
+// Each sector is solved to the absolute residual tol / sqrt(2), so that the
+// two together meet tol; a sector whose part of rhs is already below that is
+// skipped (a chiral source stays chiral: the residual b - D D^H y is chiral
+// when y is, because D D^H = D^H D commutes with gamma5).
+int sectors_solve(DOp& d, const ndq_spinor* rhs, Vecs& v, double tol, int max_iter, double* partials, double* dscal,
+                  int* iters) {
+    const ndq_geom* g = d.g;
+    hipStream_t st = d.st;
+    int rc;
+    *iters = 0;
+    if ((rc = lincomb(g, d.prec, &v.t, 0, nullptr, nullptr, nullptr, nullptr, st))) return rc;
+    for (int s = 1; s >= -1; s -= 2) {
+        const ndq_spinor* src[2] = {rhs, rhs};
+        const Coef cf[2] = {hc(0.5), hc(0.5 * s)};
+        const int g5[2] = {0, 1};
+        if ((rc = lincomb(g, d.prec, &v.e, 2, src, cf, g5, nullptr, st))) return rc;   // P_s rhs
+        double n2;
+        if ((rc = host_norm2(g, &v.e, partials, dscal, &n2, st))) return rc;
+        const double tol_abs = tol / sqrt(2.0);
+        if (sqrt(n2) <= tol_abs) continue;
+        int its = 0;
+        if ((rc = sector_cg(d, s, &v.e, &v.z, &v.s, &v.p, &v.q, tol_abs / sqrt(n2), max_iter, partials, dscal, &its)))
+            return rc;
+        *iters += its;
+        const ndq_spinor* acc[2] = {&v.t, &v.z};
+        const Coef ca[2] = {hc(1.0), hc(1.0)};
+        if ((rc = lincomb(g, d.prec, &v.t, 2, acc, ca, nullptr, nullptr, st))) return rc;
+    }
+    return NDQ_OK;
+}
+
+// out = D^H y = alpha y + beta eps (gamma5 y) with the operator of d (F64 fields);
+// tmp: work field.
+int dh_apply(DOp& d, const ndq_spinor* y, const ndq_spinor* tmp, const ndq_spinor* out) {
+    const ndq_spinor* src[2] = {y, nullptr};
+    Coef cf[2] = {hc(1.0), hc(0.0)};
+    const int g5[2] = {1, 0};
+    int rc = lincomb(d.g, d.prec, tmp, 1, src, cf, g5, nullptr, d.st);
+    if (!rc) rc = sign_apply(d, tmp);
+    if (rc) return rc;
+    src[1] = &d.S;
+    cf[0] = hc(d_alpha(d));
+    cf[1] = hc(d_beta(d));
+    return lincomb(d.g, d.prec, out, 2, src, cf, nullptr, nullptr, d.st);
+}
+
 int check_solve(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, const ndq_overlap_params* p64,
                 const ndq_overlap_params* plo, const ndq_solve_params* sp, const ndq_spinor* b, const ndq_spinor* x) {
     if (!g || !p64 || !sp) return fail(NDQ_EINVAL, "solve: NULL argument");
@@ -146,6 +286,7 @@ int check_solve(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, c
         if (Ulo->prec == NDQ_F64) return fail(NDQ_EPREC, "solve: inner links must be F32 or F16");
     }
     if (!(sp->tol > 0)) return fail(NDQ_EINVAL, "solve: tol must be positive");
+    if (sp->sectors != 0 && sp->sectors != 1) return fail(NDQ_EINVAL, "solve: sectors must be 0 or 1");
     return NDQ_OK;
 }
 
@@ -232,14 +373,28 @@ int ndq_solve_DN(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, 
             if ((rc = convert(g, &rlo, &t64, st))) return rc;
         }
         int its = 0;
-        if ((rc = cgne(dlo, &rlo, v, inner_tol, max_inner, partials, dscal, &its))) return rc;
+        const ndq_spinor* ex = &v.e;
+        if (sp->sectors) {
+            // y in the inner precision; e = D^H y with the FP64 operator, so that
+            // the next residual stays in the sectors of y (the inner operator's
+            // error would otherwise reach e amplified by |y| ~ |r| / mq^2)
+            if ((rc = sectors_solve(dlo, &rlo, v, inner_tol, max_inner, partials, dscal, &its))) return rc;
+            const ndq_spinor* y64 = &v.t;
+            if (lo != NDQ_F64) {
+                if ((rc = convert(g, &t64, &v.t, st))) return rc;
+                y64 = &t64;
+            }
+            if ((rc = dh_apply(d64, y64, &r, &r))) return rc;
+            ex = &r;
+        } else {
+            if ((rc = cgne(dlo, &rlo, v, inner_tol, max_inner, partials, dscal, &its))) return rc;
+            if (lo != NDQ_F64) {
+                if ((rc = convert(g, &t64, &v.e, st))) return rc;
+                ex = &t64;
+            }
+        }
         stt->inner += its;
         // x += |r| e
-        const ndq_spinor* ex = &v.e;
-        if (lo != NDQ_F64) {
-            if ((rc = convert(g, &t64, &v.e, st))) return rc;
-            ex = &t64;
-        }
         const ndq_spinor* s2[2] = {x, ex};
         const Coef c2[2] = {Coef{1.0, nullptr}, Coef{rn, nullptr}};
         if ((rc = lincomb(g, NDQ_F64, x, 2, s2, c2, nullptr, nullptr, st))) return rc;

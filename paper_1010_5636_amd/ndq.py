@@ -113,7 +113,7 @@ class _IndexInfo(ctypes.Structure):
 
 class _SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("inner_prec", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("inner_prec", ctypes.c_int32), ("sectors", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -522,9 +522,12 @@ def host_eigh(a):
 
 def solve_DN(geom: Geometry, U64: GaugeField, ov64: Overlap, b: SpinorField, x: SpinorField, tol: float = 1e-10,
              U_lo: GaugeField | None = None, ov_lo: Overlap | None = None, inner_prec: int = F64,
-             inner_tol: float = 0.0, max_outer: int = 20, max_inner: int = 0, stream=None) -> dict:
-    """x = (D_N^m)^{-1} b; x holds the initial guess (e.g. zeros) on entry."""
-    sp = _SolveParams(float(tol), int(max_outer), int(max_inner), float(inner_tol), int(inner_prec))
+             inner_tol: float = 0.0, max_outer: int = 20, max_inner: int = 0, sectors: bool = False,
+             stream=None) -> dict:
+    """x = (D_N^m)^{-1} b; x holds the initial guess (e.g. zeros) on entry.  ``sectors``:
+    CG on the chirality sectors of D^H D instead of CGNE."""
+    sp = _SolveParams(float(tol), int(max_outer), int(max_inner), float(inner_tol), int(inner_prec),
+                      int(bool(sectors)))
     plo = ctypes.byref(ov_lo.p) if ov_lo is not None else None
     n = int(lib().ndq_solve_workspace_bytes(geom.handle, ctypes.byref(ov64.p), plo, ctypes.byref(sp)))
     if n == 0:
