@@ -372,38 +372,41 @@ __global__ void k_mode_coef(const double* c, const double* d, ModeSigns sg, int 
 }
 
 // Basis rotation dst_j = sum_i src_i Y[i][j] for the FP64 full spinors of a
-// contiguous block (Y complex, row-major nsrc x k, on the device); each grid
-// row y computes the outputs j = 2y, 2y + 1.
+// contiguous block (Y complex, row-major nsrc x k, on the device).  One lane
+// per (complex component c, site s), sites fastest so that every load is a
+// contiguous run of one plane; grid row y computes the outputs
+// j = kRotJ y .. kRotJ y + kRotJ - 1, so each source plane is read ceil(k / kRotJ)
+// times (the coefficients are uniform across the grid row).  The sum over i
+// runs in index order for every output, as a plain loop would.
+constexpr int kRotJ = 16;
 __global__ void __launch_bounds__(kBlock) k_rotate(const char* __restrict__ src, int nsrc, const double* __restrict__ Y,
                                                    int k, char* __restrict__ dst, int64_t vbytes, SpinorView lay,
                                                    int32_t n) {
-    const int32_t s = blockIdx.x * kBlock + threadIdx.x;
-    if (s >= n) return;
-    const int j0 = 2 * blockIdx.y;
-    const bool two = j0 + 1 < k;
-    C<double> a0[12], a1[12];
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= 12 * (int64_t)n) return;
+    const int c = (int)(t / n);
+    const int32_t s = (int32_t)(t - (int64_t)c * n);
+    const int j0 = kRotJ * blockIdx.y;
+    const int cnt = min(kRotJ, k - j0);
+    C<double> acc[kRotJ];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) a0[c] = a1[c] = {0.0, 0.0};
+    for (int j = 0; j < kRotJ; ++j) acc[j] = {0.0, 0.0};
     for (int i = 0; i < nsrc; ++i) {
         SpinorView v = lay;
         v.base = const_cast<char*>(src) + (int64_t)i * vbytes;
-        C<double> x[12];
-        SpinorIO<P64>::load(v, s, x);
-        const C<double> y0 = {Y[2 * ((int64_t)i * k + j0)], Y[2 * ((int64_t)i * k + j0) + 1]};
+        const C<double> x = SpinorIO<P64>::load_comp(v, s, c);
+        const double* yi = Y + 2 * ((int64_t)i * k + j0);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) a0[c] = cfma(a0[c], y0, x[c]);
-        if (two) {
-            const C<double> y1 = {Y[2 * ((int64_t)i * k + j0 + 1)], Y[2 * ((int64_t)i * k + j0 + 1) + 1]};
-#pragma unroll
-            for (int c = 0; c < 12; ++c) a1[c] = cfma(a1[c], y1, x[c]);
-        }
+        for (int j = 0; j < kRotJ; ++j)
+            if (j < cnt) acc[j] = cfma(acc[j], C<double>{yi[2 * j], yi[2 * j + 1]}, x);
     }
-    SpinorView o = lay;
-    o.base = dst + (int64_t)j0 * vbytes;
-    SpinorIO<P64>::store(o, s, a0);
-    if (two) {
-        o.base += vbytes;
-        SpinorIO<P64>::store(o, s, a1);
+#pragma unroll
+    for (int j = 0; j < kRotJ; ++j) {
+        if (j < cnt) {
+            SpinorView o = lay;
+            o.base = dst + (int64_t)(j0 + j) * vbytes;
+            SpinorIO<P64>::store_comp(o, s, c, acc[j]);
+        }
     }
 }
 
@@ -683,7 +686,8 @@ int rotate(const ndq_geom* g, const void* src, int nsrc, const double* Y, int k,
     ndq_spinor d = {const_cast<void*>(src), NDQ_F64, NDQ_FULL, 1};
     const SpinorView lay = flat_view(g, &d);
     const int64_t vb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
-    const dim3 grid(nblocks(g->volume), (k + 1) / 2);
+    const int64_t lanes = 12 * (int64_t)g->volume;
+    const dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock), (k + kRotJ - 1) / kRotJ);
     hipLaunchKernelGGL(k_rotate, grid, dim3(kBlock), 0, st, static_cast<const char*>(src), nsrc, Y, k,
                        static_cast<char*>(dst), vb, lay, (int32_t)g->volume);
     NDQ_HIP(hipGetLastError());
