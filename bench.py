@@ -149,7 +149,8 @@ def solve_leg(log):
     ov64 = ndq.Overlap(g, M, ap64, LAM_MAX, modes=modes, nu=nu, mq=SOLVE_MQ)
     ov_lo = ndq.Overlap(g, M, ap_lo, LAM_MAX, modes=modes, nu=nu, mq=SOLVE_MQ)
     out = {"workload": "D_N^m x = b, 24^3x48, m=-1.4, mq=0.05, 20 exact low modes (FP64 block Chebyshev-filtered subspace iteration), "
-                       "complex Gaussian b, true relative residual 1e-10 with the FP64 operator",
+                       "complex Gaussian b (and a chiral point source for the inner-solver comparison), true relative "
+                       "residual 1e-10 with the FP64 operator",
            "dims": list(SOLVE_DIMS), "setup_s": {"fields": round(t_fields, 2), "lowmodes": round(t_modes, 2),
                                                  "approximants": round(t_approx, 2)},
            "lowmodes": {"nev": SOLVE_NEV, "nu_abs_min": float(np.abs(nu).min()), "nu_abs_max": float(np.abs(nu).max()),
