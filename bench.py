@@ -474,11 +474,35 @@ def autograd_leg(log):
     # per site: its 4 links, psi and g once each (the x + mu neighbours are
     # other sites' own values), 4 x 8 force components written
     bytes_site = 4 * 144 + 2 * 192 + 4 * 8 * 8
+    # gradient error: dS along one random su(3) direction omega (U -> exp(i h omega.T) U)
+    # by central differences of S = |Q psi|^2, against sum omega . F with F the force
+    # of the cotangent 2 Q psi
+    y0 = ndq.SpinorField(g, ndq.F64, ndq.FULL)
+    ndq.apply_Q(g, U, M, x, y0)
+    gy2 = ndq.SpinorField.pack(g, 2.0 * y0.unpack()[0], ndq.F64, ndq.FULL)
+    force = ndq.gauge_force(g, U, x, gy2)[0]
+    om = torch.from_numpy(synthetic.su3_directions(v, 1, seed=synthetic.SEED_DIRECTIONS)[0]).to(dev)
+    analytic = float((om * force).sum())
+    gen = torch.from_numpy(synthetic.su3_generators()).to(dev)
+    hmat = torch.einsum("vma,aij->vmij", om.to(torch.complex128), gen)
+    h = 1e-5
+
+    def action(sgn):
+        up = torch.linalg.matrix_exp(1j * sgn * h * hmat) @ links.detach()
+        Uh = ndq.GaugeField.pack(g, up.contiguous(), ndq.F64, 18)
+        yh = ndq.SpinorField(g, ndq.F64, ndq.FULL)
+        ndq.apply_Q(g, Uh, M, x, yh)
+        return float((yh.buf.view(torch.float64) ** 2).sum())
+
+    fd = (action(1) - action(-1)) / (2 * h)
+    grad_err = abs(fd - analytic) / abs(analytic)
     out = {"workload": "S = psi^H Q^2 psi, 16^3x32, FP64, 18-real links",
            "autograd_step_ms": round(ms_step, 4), "force_kernel_us": round(ms_f * 1e3, 2),
+           "gradient_check": {"direction": "random su(3), seed 1004", "h": h, "central_difference": fd,
+                              "analytic": analytic, "rel_error": grad_err},
            "force_alg_bytes": bytes_site * v,
            "force_hbm_gbs": round(bytes_site * v / (ms_f * 1e-3) / 1e9, 1)}
-    log(f"autograd leg: step {ms_step:.3f} ms, force kernel {ms_f * 1e3:.1f} us")
+    log(f"autograd leg: step {ms_step:.3f} ms, force kernel {ms_f * 1e3:.1f} us, gradient rel. error {grad_err:.1e}")
     return out
 
 
@@ -604,6 +628,25 @@ def main():
             "launch": launch,
             "autotune_us": None if tune is None else {k: round(t, 3) for k, t in tune["us"].items()},
         }
+        if (name, sp, lp, recon) == fmts[0] and not args.warm_cache:
+            # the same dslash on one buffer set (37.7 MB at F32-12, resident in the
+            # 256 MB last-level cache): the cache-warm rate, next to the HBM-streamed one
+            U0, e0, o0 = sets[0]
+            warm = {"k": 0}
+
+            def warm_step():
+                if warm["k"] % 2 == 0:
+                    ndq.apply_dslash(g, U0, e0, o0)
+                else:
+                    ndq.apply_dslash(g, U0, o0, e0)
+                warm["k"] += 1
+
+            for _ in range(20):
+                warm_step()
+            us_warm = _time_events(warm_step, args.steps) * 1e3
+            results[name]["warm_cache"] = {"us": round(us_warm, 3),
+                                           "gflops": round(FLOP_PER_SITE * vh / (us_warm * 1e-6) / 1e9, 1),
+                                           "alg_gbs": round(alg_bytes / (us_warm * 1e-6) / 1e9, 1)}
         if (name, sp, lp, recon) == fmts[0] and not args.graph:
             # the even-site Schur operator Qhat_ee (two dslashes and the site
             # term) and the dslash replayed from a captured graph of 2 x nsets launches
