@@ -91,9 +91,34 @@ def cpu_baseline(max_seconds=20.0):
             if (n >= 2 and el > max_seconds) or n >= 50:
                 break
     gflops = FLOP_PER_SITE * (v // 2) * n / el / 1e9
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    # per output site of one dslash; a full Q is two dslashes (both parities) plus the
+    # site term, so about 2 x this per site of the lattice
+    us_site = el / n / (v // 2) * 1e6
     return {"value": round(gflops, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} even/odd dslash applies of the FP64 numpy oracle on the 16^3x32 lattice "
-                      f"({el:.1f} s, one thread)"}
+                      f"({el:.1f} s, one thread)",
+            "host": {"cpu": cpu, "nproc": os.cpu_count()}, "us_per_site_dslash": round(us_site, 4)}
+
+
+def extrapolated_cpu(base, solve):
+    """Oracle times the CPU could not run in a bounded sample, extrapolated from the
+    measured per-site dslash time (labelled as such): the paper's tau (time per site per
+    Clenshaw step = 2 full Q applies, vector work ignored), and one plain FP64 solve on
+    24^3x48 from the GPU run's count of Q applies."""
+    t_q_site = 2 * base["us_per_site_dslash"]
+    v = int(np.prod(SOLVE_DIMS))
+    out = {"kind": "extrapolated from the measured oracle dslash rate (one thread)",
+           "tau_us_clenshaw_step": round(2 * t_q_site, 4)}
+    if solve:
+        out["fp64_solve_24c48_s"] = round(solve["runs"]["fp64"]["q_applies"] * t_q_site * v * 1e-6, 1)
+        out["fp64_solve_gpu_s"] = solve["runs"]["fp64"]["seconds"]
+    return out
 
 
 SOLVE_DIMS = (48, 24, 24, 24)
@@ -727,6 +752,7 @@ def main():
         out["index"] = index_leg(log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"]["extrapolated"] = extrapolated_cpu(out["cpu_baseline"], out.get("dn_solve"))
     print(json.dumps(out), flush=True)
     return 0
 
