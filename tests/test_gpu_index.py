@@ -112,8 +112,8 @@ def test_block_too_small(free):
 
 @pytest.mark.parametrize("q23,want", [(1, -2), (-1, 2)])
 def test_index_theorem_8x4(q23, want):
-    """8^4 flux backgrounds (no dense oracle): index = -2 q01 q23 in this
-    build's convention (the oracle's sign, pinned on 4^4)."""
+    """8^4 flux backgrounds (no dense oracle): index = -2 q01 q23 in the
+    chirality convention used here (the oracle's sign, pinned on 4^4)."""
     dims = (8, 8, 8, 8)
     u = synthetic.flux_gauge_field(dims, 1, q23, noise=0.2, gauge_seed=synthetic.SEED_HAAR)
     g = ndq.Geometry(dims)

@@ -68,7 +68,7 @@ def test_free_field_constant_zero_modes(free):
 def test_index_theorem_on_flux_backgrounds(flux_pp, flux_pm):
     """Fluxes (q01, q23) = (1, +-1) in the diag(e^{i phi}, e^{-i phi}, 1)
     embedding: |Q_top| = 2 |q01 q23| = 2, with opposite signs; light noise and a
-    gauge transformation leave it unchanged.  In this build's convention the
+    gauge transformation leave it unchanged.  With the chirality convention used here the
     index n_+ - n_- is -2 q01 q23."""
     assert flux_pp.svd["index"] == -2
     assert (flux_pp.count["n_plus"], flux_pp.count["n_minus"]) == (flux_pp.svd["n_plus"], flux_pp.svd["n_minus"])
