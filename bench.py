@@ -185,6 +185,9 @@ def solve_leg(log):
            "approximant": {"kind": "minimax polynomial (Clenshaw)", "eps": eps, "degree_fp64": ap64.n,
                            "delta_fp64": ap64.delta, "degree_inner": ap_lo.n, "delta_inner": ap_lo.delta}}
     runs = {}
+    # Inner tolerances: 1e-5 for F32 storage (two outer steps); 4e-3 for F16 storage,
+    # the fastest of 5e-4 .. 2e-2 measured on this workload (F16 rounding limits each
+    # inner solve to ~1e-3 anyway).
     # a spin-colour point source (spin 2, colour 0 at site 0): chiral, so the
     # chirality-sector inner solver needs one sector
     point = torch.zeros((v, 4, 3), dtype=torch.complex128, device=dev)
@@ -193,7 +196,7 @@ def solve_leg(log):
     del point
     for name, prec, Ulo, ovlo, itol, sectors, rhs in (
             ("mixed_f32", ndq.F32, U32, ov_lo, 0.0, False, b),
-            ("mixed_f16", ndq.F16, U16, ov_lo, 2e-3, False, b),
+            ("mixed_f16", ndq.F16, U16, ov_lo, 4e-3, False, b),
             ("fp64", ndq.F64, None, None, 0.0, False, b),
             ("point_mixed_f32", ndq.F32, U32, ov_lo, 0.0, False, b_point),
             ("point_mixed_f32_sectors", ndq.F32, U32, ov_lo, 0.0, True, b_point),
