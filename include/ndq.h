@@ -262,6 +262,9 @@ size_t ndq_solve_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p6
  * solve D e = r/|r| by CG on the normal equations (D^H = gamma5 D gamma5), or by
  * CG on their chirality sectors (sp->sectors), in the inner precision (U_lo and p_lo: F32 arithmetic on F32 or F16 storage, with their
  * own approximant; or FP64 with U64, p64 for the plain solve) and set x += |r| e.
+ * Both operators apply Eq. 11 in its sandwich form whatever p64->form and
+ * p_lo->form say: CG on the normal equations needs D^H = gamma5 D gamma5, i.e. a
+ * Hermitian sign(Q), which the literal form is only up to O(rho_k).
  * b, x: F64 NDQ_FULL, nrhs 1; x holds the initial guess on entry.  Synchronises
  * `stream`.  stats: outer steps, inner CG iterations, Q applications, final true
  * relative residual.  Errors: NDQ_ENOCONV, NDQ_ENOMEM, NDQ_ENAN, NDQ_EPREC. */
@@ -295,8 +298,10 @@ enum { NDQ_LM_SUBSPACE = 0, NDQ_LM_LANCZOS = 1, NDQ_LM_RITZ = 2 };
 typedef struct {
     double lam_next;      /* |Q u| of the guard vector u (the next Ritz vector after the
                              nev returned, in the order of |Q u|^2)                          */
-    double kappa_plus;    /* Eq. 9, with d_k = min(lam_next - |nu_k|, |nu_k| + min|nu_j| over */
-    double kappa_minus;   /*   the returned nu_j of opposite sign)                             */
+    double kappa_plus;    /* Eq. 9, with d_k = min(lam_next - rho_next - |nu_k|, |nu_k| + min|nu_j|
+                             over the returned nu_j of opposite sign): lam_next - rho_next is
+                             the certified lower end of the rest of the spectrum of |Q|      */
+    double kappa_minus;
     double bound_plus;    /* Eq. 10: |P_+ - (P_+)_exact| <= kappa(1+2kappa)/(1-2kappa(1+2kappa)) */
     double bound_minus;
     double cheb_lo;       /* filter cutoff used                                               */
@@ -378,7 +383,8 @@ typedef struct {
 size_t ndq_index_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p, const ndq_index_params* params);
 
 /*   U: FP64 links;  p: overlap parameters (approximant, lam_max, Wilson mass m, optional
- *   exact low modes of Q; mq is not used);  params: NULL for the defaults;
+ *   exact low modes of Q; mq is not used; the projection of Eq. 11 is applied in its
+ *   sandwich form, so that A_s is Hermitian);  params: NULL for the defaults;
  *   start: one nonzero FP64 NDQ_FULL field (the block start vectors are phase-
  *   randomised, chirally projected copies);  info: out (filled also on error).
  *   Synchronises `stream`.  Errors: NDQ_EINVAL, NDQ_EPREC, NDQ_ENOMEM (workspace),

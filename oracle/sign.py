@@ -117,30 +117,45 @@ def sign_approx(apply_q, psi, approximant, lam_max, tol: float = 1e-13):
     return sign_polynomial(apply_q, psi, approximant, lam_max)
 
 
+def _field_dot(u: np.ndarray, psi: np.ndarray):
+    """<u, psi> summed over the field axes of u; psi may carry leading batch axes
+    (one inner product per field of the batch)."""
+    axes = tuple(range(-u.ndim, 0))
+    return np.sum(u.conj() * psi, axis=axes)
+
+
+def _times_mode(c, u: np.ndarray) -> np.ndarray:
+    """c u for a scalar or a batch of coefficients c (one per field of a batch)."""
+    c = np.asarray(c)
+    return c.reshape(c.shape + (1,) * u.ndim) * u
+
+
 def project_literal(apply_approx, modes: np.ndarray, nu: np.ndarray, psi: np.ndarray) -> np.ndarray:
     """Eq. 11 as printed: (P_+ - P_-) psi + (1 - P_+ - P_-) [X P(X^2) psi].
 
     ``modes`` is [l, ...field shape] with orthonormal rows u_k; ``nu`` the
-    Rayleigh-Ritz eigenvalues (P Q u_k = nu_k u_k).
+    Rayleigh-Ritz eigenvalues (P Q u_k = nu_k u_k).  ``psi`` is one field or a
+    batch of fields (leading axes); each is projected on its own.
     """
     if np.any(nu == 0):
         raise ValueError("a low mode with nu_k = 0 has no sign")
     t = apply_approx(psi)
     out = t.copy()
     for u, n in zip(modes, nu):
-        out = out + (np.sign(n) * _vdot(u, psi) - _vdot(u, t)) * u
+        out = out + _times_mode(np.sign(n) * _field_dot(u, psi) - _field_dot(u, t), u)
     return out
 
 
 def project_sandwich(apply_approx, modes: np.ndarray, nu: np.ndarray, psi: np.ndarray) -> np.ndarray:
-    """(P_+ - P_-) psi + (1 - P) r(X) (1 - P) psi (exactly Hermitian variant)."""
+    """(P_+ - P_-) psi + (1 - P) r(X) (1 - P) psi (exactly Hermitian variant);
+    ``psi`` one field or a batch of fields as in ``project_literal``."""
     if np.any(nu == 0):
         raise ValueError("a low mode with nu_k = 0 has no sign")
     rest = psi.copy()
     for u in modes:
-        rest = rest - _vdot(u, psi) * u
+        rest = rest - _times_mode(_field_dot(u, psi), u)
     t = apply_approx(rest)
     out = t.copy()
     for u, n in zip(modes, nu):
-        out = out + np.sign(n) * _vdot(u, psi) * u - _vdot(u, t) * u
+        out = out + _times_mode(np.sign(n) * _field_dot(u, psi), u) - _times_mode(_field_dot(u, t), u)
     return out

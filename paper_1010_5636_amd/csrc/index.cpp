@@ -293,7 +293,8 @@ size_t ndq_index_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p,
     ndq_index_params ip;
     with_defaults(params, ip);
     if (ip.block < 2 || ip.block > 64) return 0;
-    return index_workspace(g, p, ip);
+    const ndq_overlap_params ph = hermitian_form(p);
+    return index_workspace(g, &ph, ip);
 }
 
 int ndq_index_DN(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p, const ndq_index_params* params,
@@ -313,6 +314,9 @@ int ndq_index_DN(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params
     if (start->prec != NDQ_F64 || start->nrhs != 1 || U->prec != NDQ_F64)
         return fail(NDQ_EPREC, "index: FP64 links and one FP64 start field required");
     if (!p->approx) return fail(NDQ_EINVAL, "index: no approximant");
+    // A_s must be Hermitian for its Rayleigh-Ritz step: sandwich projection
+    const ndq_overlap_params ph = hermitian_form(p);
+    p = &ph;
     const size_t need = index_workspace(g, p, ip);
     if (!ws || ws_bytes < need) return fail(NDQ_ENOMEM, "index: workspace too small (need %zu bytes)", need);
 

@@ -686,10 +686,13 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
         memset(info, 0, sizeof(*info));
         info->lam_next = lam_next;
         info->nev_used = l_used;
-        // Eq. 9 with d_k = min(lam_next - |nu_k|, |nu_k| + min over opposite-sign |nu_j|)
+        // Eq. 9 with d_k = min(lam_lo - |nu_k|, |nu_k| + min over opposite-sign |nu_j|),
+        // lam_lo = lam_next - rho_next the certified lower end of the rest of |spectrum|,
+        // so that kappa and the Eq. 10 bounds err on the safe side
+        const double lam_lo = lam_next - rho_next;
         double kp2 = 0.0, km2 = 0.0;
         for (int k = 0; k < l_used; ++k) {
-            double dk = lam_next - fabs(nu[k]);
+            double dk = lam_lo - fabs(nu[k]);
             for (int j = 0; j < l_used; ++j)
                 if ((nu[j] > 0) != (nu[k] > 0)) dk = std::min(dk, fabs(nu[k]) + fabs(nu[j]));
             const double q = dk > 0 ? rho[k] / dk : INFINITY;

@@ -131,6 +131,17 @@ int ms_update(const ndq_geom* g, int prec, MsState* st_dev, const MsConst& k, co
               const ndq_spinor* y, const ndq_spinor* p, double* partials, hipStream_t st);
 
 // ---- sign and D_N (sign.cpp) --------------------------------------------------
+// The overlap parameters with the projection of Eq. 11 in the sandwich form
+// (1 - P) r(X) (1 - P) + P_+ - P_-, which keeps sign(Q) exactly Hermitian for
+// inexact modes (the literal form differs by the commutator [r(X), P] = O(rho)).
+// Used where an algorithm relies on that symmetry: CG on the normal equations
+// (D^H = gamma5 D gamma5) and the Hermitian sector operators of the index.
+inline ndq_overlap_params hermitian_form(const ndq_overlap_params* p) {
+    ndq_overlap_params q = *p;
+    q.form = NDQ_SANDWICH;
+    return q;
+}
+
 size_t sign_workspace(const ndq_geom* g, const ndq_overlap_params* p, int prec);
 int apply_sign(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p, const ndq_spinor* in,
                const ndq_spinor* out, Arena& ar, ndq_stats* stats, hipStream_t st);

@@ -4,7 +4,8 @@
 // stop once |r| <= tol |b|; otherwise solve D e = r / |r| approximately in the
 // inner precision and update x += |r| e.  Inner solver: CG on the normal
 // equations D^H D e = D^H r (CGNE) with D^H = gamma5 D gamma5, which holds
-// because sign(Q) is Hermitian.  With inner precision F64 and an inner
+// because sign(Q) is Hermitian (the solve applies the projection of Eq. 11 in
+// its sandwich form, Hermitian also for inexact low modes).  With inner precision F64 and an inner
 // tolerance at the target this is the plain FP64 solve (normally one outer
 // step plus the final true-residual check); with F32 (or F16 storage) the
 // inner solves run in FP32 arithmetic on cheaper fields and approximant, and
@@ -297,9 +298,13 @@ using namespace ndq;
 
 extern "C" {
 
-size_t ndq_solve_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p64, const ndq_overlap_params* plo,
+size_t ndq_solve_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p64_in, const ndq_overlap_params* plo_in,
                                  const ndq_solve_params* sp) {
-    if (!g || !p64 || !p64->approx || !sp) return 0;
+    if (!g || !p64_in || !p64_in->approx || !sp) return 0;
+    const ndq_overlap_params h64 = hermitian_form(p64_in);
+    const ndq_overlap_params hlo = plo_in ? hermitian_form(plo_in) : h64;
+    const ndq_overlap_params* p64 = &h64;
+    const ndq_overlap_params* plo = plo_in ? &hlo : nullptr;
     const int lo = sp->inner_prec;
     const ndq_overlap_params* pi = lo == NDQ_F64 ? p64 : plo;
     if (!pi || !pi->approx) return 0;
@@ -312,15 +317,21 @@ size_t ndq_solve_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p6
     return b + std::max(s64, slo) + 4096;
 }
 
-int ndq_solve_DN(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, const ndq_overlap_params* p64,
-                 const ndq_overlap_params* plo, const ndq_solve_params* sp, const ndq_spinor* b, const ndq_spinor* x,
+int ndq_solve_DN(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, const ndq_overlap_params* p64_in,
+                 const ndq_overlap_params* plo_in, const ndq_solve_params* sp, const ndq_spinor* b, const ndq_spinor* x,
                  void* ws, size_t ws_bytes, ndq_stats* stats, void* stream) {
     const auto t0 = std::chrono::steady_clock::now();
     ndq_stats local;
     ndq_stats* stt = stats ? stats : &local;
     memset(stt, 0, sizeof(*stt));
-    int rc = check_solve(g, U64, Ulo, p64, plo, sp, b, x);
+    int rc = check_solve(g, U64, Ulo, p64_in, plo_in, sp, b, x);
     if (rc) return rc;
+    // CGNE takes D^H = gamma5 D gamma5, which needs a Hermitian sign(Q): the
+    // operators of the solve use the sandwich form of Eq. 11
+    const ndq_overlap_params h64 = hermitian_form(p64_in);
+    const ndq_overlap_params hlo = plo_in ? hermitian_form(plo_in) : h64;
+    const ndq_overlap_params* p64 = &h64;
+    const ndq_overlap_params* plo = plo_in ? &hlo : nullptr;
     hipStream_t st = as_stream(stream);
     const int lo = sp->inner_prec;
     const ndq_gauge* Ui = lo == NDQ_F64 ? U64 : Ulo;

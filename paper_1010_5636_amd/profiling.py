@@ -1,7 +1,16 @@
-"""Summaries of rocprofv3 output for the stencil kernels.
+"""Summaries of rocprofv3 output for the stencil kernels, and the workloads they profile.
 
     python -m paper_1010_5636_amd.profiling stats   <out.txt> <cmd> <label>=<trace_dir> ...
     python -m paper_1010_5636_amd.profiling traffic <out.json> <copy_bytes> <cmd> <block,xcd>=<fetch_dir>,<write_dir> ...
+    python -m paper_1010_5636_amd.profiling kernels <out.txt> <copy_bytes> <cmd> <trace_dir> <fetch_dir> <write_dir>
+    python -m paper_1010_5636_amd.profiling run <workload>[,<workload>...] [reps]
+
+``run`` executes fixed, seeded workloads of the solve and batching legs for the
+profiler (``WORKLOADS`` below), each a few launches of the kernels it names,
+followed by a device copy of 512 MiB for the counter calibration.  ``kernels``
+joins one kernel-trace run and one FETCH_SIZE and one WRITE_SIZE run of the
+same command into a per-kernel table: average duration, and HBM bytes per
+dispatch (median) scaled by the calibration copy.
 
 ``stats`` condenses ``*kernel_stats.csv`` (from ``rocprofv3 --kernel-trace
 --stats``) of one or more runs into a short text table, one section per run.
@@ -24,7 +33,7 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_1010_5636_amd/csrc/wilson.hip", "paper_1010_5636_amd/csrc/wilson.h",
-                  "paper_1010_5636_amd/csrc/ndq_device.h"]
+                  "paper_1010_5636_amd/csrc/ndq_device.h", "paper_1010_5636_amd/csrc/blas.hip"]
 _FMT = re.compile(r"k_wilson(_dirsplit)?<(\d+), (\d+), (\d+)")
 _PREC = {0: "f64", 1: "f32", 2: "f16"}
 
@@ -136,6 +145,156 @@ def lookup(rec: dict, fmt: str, launch: dict):
     return None
 
 
+def kernels_text(trace_dir: str, fetch_dir: str, write_dir: str, copy_bytes: int, command: str) -> str:
+    """Per-kernel time and HBM traffic of one workload (see the module docstring)."""
+    stats = {r["name"]: r for r in kernel_stats(trace_dir)}
+    fetch = counters(fetch_dir, "FETCH_SIZE")
+    write = counters(write_dir, "WRITE_SIZE")
+    cf = _copy_reading(fetch, copy_bytes)
+    cw = _copy_reading(write, copy_bytes)
+    if not cf or not cw:
+        raise RuntimeError("calibration copy kernel not found in the counter output")
+    sf, sw = copy_bytes / cf, copy_bytes / cw
+    lines = ["# rocprofv3 kernel time and HBM traffic per dispatch", f"# command: {command}",
+             f"# kernel source hash: {kernel_hash()}",
+             f"# counter scale from a {copy_bytes}-byte device copy: {sf:.2f} bytes per FETCH_SIZE unit, "
+             f"{sw:.2f} per WRITE_SIZE unit", "",
+             f"{'calls':>7}{'avg_us':>11}{'fetch_MB':>11}{'write_MB':>11}{'GB/s':>9}  kernel"]
+    rows = sorted(stats.values(), key=lambda r: -r["calls"] * r["avg_ns"])
+    for r in rows:
+        f = fetch.get(r["name"])
+        w = write.get(r["name"])
+        fb = sf * sorted(f)[len(f) // 2] if f else float("nan")
+        wb = sw * sorted(w)[len(w) // 2] if w else float("nan")
+        gbs = (fb + wb) / r["avg_ns"] if f and w else float("nan")
+        lines.append(f"{r['calls']:>7}{r['avg_ns'] / 1e3:>11.3f}{fb / 1e6:>11.3f}{wb / 1e6:>11.3f}{gbs:>9.1f}  "
+                     f"{r['name'][:120]}")
+    return "\n".join(lines) + "\n"
+
+
+# ---- profiled workloads -------------------------------------------------------
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _fullq24(reps):
+    """Full Q on 24^3 x 48 (the solve lattice) in the solver's formats: F32
+    spinors with 12-real F32 links, F16 spinors with 12-real F16 links, F64 with
+    18-real links; two rotating field sets per format."""
+    import torch
+    import synthetic
+    import paper_1010_5636_amd as ndq
+    dims = (48, 24, 24, 24)
+    g = ndq.Geometry(dims)
+    u = torch.from_numpy(synthetic.gauge_field(dims)).cuda()
+    psi = torch.from_numpy(synthetic.spinor(g.volume)).cuda()
+    for sp, lp, recon in ((ndq.F32, ndq.F32, 12), (ndq.F16, ndq.F16, 12), (ndq.F64, ndq.F64, 18)):
+        sets = []
+        for k in range(2):
+            U = ndq.GaugeField.pack(g, u, lp, recon)
+            x = ndq.SpinorField.pack(g, psi * (1 + 0.1 * k), sp, ndq.FULL)
+            sets.append((U, x, x.like()))
+        for i in range(reps):
+            U, x, y = sets[i % 2]
+            ndq.apply_Q(g, U, -1.4, x, y)
+        torch.cuda.synchronize()
+        _log(f"fullq24: format ({sp}, {lp}, {recon}) done")
+        del sets
+
+
+def _mrhs32(reps):
+    """The 12 spin-colour point sources on 32^3 x 64 (F32 spinors, 18-real F32
+    links) in one multi-RHS Q apply."""
+    import torch
+    import synthetic
+    import paper_1010_5636_amd as ndq
+    dims = (64, 32, 32, 32)
+    g = ndq.Geometry(dims)
+    U = ndq.GaugeField.pack(g, torch.from_numpy(synthetic.gauge_field(dims)).cuda(), ndq.F32, 18)
+    canon = torch.zeros((12, g.volume, 4, 3), dtype=torch.complex128, device="cuda")
+    for s in range(4):
+        for c in range(3):
+            canon[3 * s + c, 0, s, c] = 1.0
+    x = ndq.SpinorField.pack(g, canon, ndq.F32, ndq.FULL)
+    del canon
+    y = x.like()
+    for _ in range(reps):
+        ndq.apply_Q(g, U, -1.4, x, y)
+    torch.cuda.synchronize()
+    _log("mrhs32: done")
+
+
+def _filter24(reps):
+    """The low-mode filter's block apply: Q on 60 FP64 fields (18-real links) on 24^3 x 48."""
+    import torch
+    import synthetic
+    import paper_1010_5636_amd as ndq
+    dims = (48, 24, 24, 24)
+    g = ndq.Geometry(dims)
+    U = ndq.GaugeField.pack(g, torch.from_numpy(synthetic.gauge_field(dims)).cuda(), ndq.F64, 18)
+    x = ndq.SpinorField(g, ndq.F64, ndq.FULL, 60)
+    one = ndq.SpinorField.pack(g, torch.from_numpy(synthetic.spinor(g.volume)).cuda(), ndq.F64, ndq.FULL)
+    rb = g.spinor_bytes(ndq.F64, ndq.FULL, 1)
+    for r in range(60):
+        x.buf[r * rb:(r + 1) * rb].copy_(one.buf)
+    y = x.like()
+    for _ in range(reps):
+        ndq.apply_Q(g, U, -1.4, x, y)
+    torch.cuda.synchronize()
+    _log("filter24: done")
+
+
+def _modes24(reps):
+    """The low-mode projection of Eq. 11 with 20 FP64 modes on 24^3 x 48: sign
+    applies with a degree-1 polynomial (so the projection kernels dominate) on
+    F32 and F64 fields."""
+    import torch
+    import synthetic
+    import paper_1010_5636_amd as ndq
+    import numpy as np
+    dims = (48, 24, 24, 24)
+    g = ndq.Geometry(dims)
+    u = torch.from_numpy(synthetic.gauge_field(dims)).cuda()
+    nev = 20
+    modes = ndq.SpinorField(g, ndq.F64, ndq.FULL, nev)
+    one = ndq.SpinorField.pack(g, torch.from_numpy(synthetic.spinor(g.volume)).cuda(), ndq.F64, ndq.FULL)
+    rb = g.spinor_bytes(ndq.F64, ndq.FULL, 1)
+    for r in range(nev):
+        modes.buf[r * rb:(r + 1) * rb].copy_(one.buf)
+    nu = np.linspace(-0.5, 0.5, nev) + 0.01
+    ap = ndq.Approx(ndq.MINMAX_POLY, 0.01, 1)
+    for sp, lp, recon in ((ndq.F32, ndq.F32, 12), (ndq.F64, ndq.F64, 18)):
+        U = ndq.GaugeField.pack(g, u, lp, recon)
+        ov = ndq.Overlap(g, -1.4, ap, 6.6, modes=modes, nu=nu)
+        x = ndq.SpinorField.pack(g, torch.from_numpy(synthetic.spinor(g.volume)).cuda(), sp, ndq.FULL)
+        y = x.like()
+        for _ in range(reps):
+            ndq.apply_sign(g, U, ov, x, y)
+        torch.cuda.synchronize()
+    _log("modes24: done")
+
+
+WORKLOADS = {"fullq24": _fullq24, "mrhs32": _mrhs32, "filter24": _filter24, "modes24": _modes24}
+CALIBRATION_BYTES = 512 * 1024 * 1024
+
+
+def run(names, reps: int) -> int:
+    import torch
+    from . import ndq
+    ndq.lib()
+    for name in names:
+        _log(f"workload {name}: {reps} reps")
+        WORKLOADS[name](reps)
+    src = torch.empty(CALIBRATION_BYTES, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    _log("calibration copy done")
+    return 0
+
+
 def _launch(text: str) -> dict:
     b, x = (int(t) for t in text.split(","))
     return {"block": b, "xcd_remap": x}
@@ -159,6 +318,15 @@ def main(argv):
         with open(argv[1], "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec, indent=1))
+        return 0
+    if len(argv) >= 2 and argv[0] == "run":
+        sys.path.insert(0, ROOT)
+        return run(argv[1].split(","), int(argv[2]) if len(argv) > 2 else 10)
+    if len(argv) == 7 and argv[0] == "kernels":
+        txt = kernels_text(argv[4], argv[5], argv[6], int(argv[2]), argv[3])
+        with open(argv[1], "w") as fh:
+            fh.write(txt)
+        print(txt)
         return 0
     print(__doc__)
     return 2

@@ -7,6 +7,9 @@
 * 8^4 random links, l = 12: residues recomputed by the oracle's stencil.
 * 4^4 free field, l = 48 (block method): the exactly 48-fold degenerate
   |lambda| = 0.6 eigenspace, projector against the exact one.
+* every run: the library's kappa_+-, Eq. 10 bounds (Eq. 9, Eq. 10) against the
+  oracle's gap_distances / kappas / projector_bound evaluated on the library's
+  own nu, rho and certified lower gap lam_next - rho_next (relative 1e-10).
 All three methods (block subspace iteration, thick-restart Lanczos, and the
 paper's Ritz-functional minimisation) are exercised.
 """
@@ -45,6 +48,19 @@ def run(dims, u, nev, nextra=8, tol=1e-11, basis=0, method=ndq.ndq.LM_SUBSPACE):
 METHODS = [ndq.ndq.LM_SUBSPACE, ndq.ndq.LM_LANCZOS, ndq.ndq.LM_RITZ]
 
 
+def check_diagnostics(nu, rho, info):
+    """kappa_+- and the Eq. 10 bounds of the library against the oracle's
+    formulas on the same nu, rho and lower gap (first nev_used modes)."""
+    l = info["nev_used"]
+    d = lowmodes.gap_distances(nu[:l], info["lam_next"] - info["rho_next"])
+    kp, km = lowmodes.kappas(nu[:l], rho[:l], d)
+    for got, ref in ((info["kappa_plus"], kp), (info["kappa_minus"], km),
+                     (info["bound_plus"], lowmodes.projector_bound(kp)),
+                     (info["bound_minus"], lowmodes.projector_bound(km))):
+        assert abs(got - ref) <= 1e-10 * abs(ref) + 1e-300, (got, ref, info)
+    assert info["rho_next"] >= 0.0 and info["lam_next"] - info["rho_next"] > np.abs(nu[:l]).max()
+
+
 @pytest.fixture(scope="module")
 def dense4():
     u = synthetic.gauge_field((4, 4, 4, 4))
@@ -67,6 +83,8 @@ def test_lowmodes_random_4c4(dense4, method):
     rho_o = np.linalg.norm(qu - nu[:, None] * um, axis=1)
     assert np.allclose(rho, rho_o, rtol=1e-3, atol=1e-13)
     assert abs(info["lam_next"] - abs(lam[nev])) < 1e-6
+    assert info["lam_next"] - info["rho_next"] <= abs(lam[nev]) + 1e-12
+    check_diagnostics(nu, rho, info)
     # Eq. 10 against the true projector deviation
     nu_ex, m_ex = lowmodes.dense_lowmodes(dense4["q"], nev, eig=dense4["eig"])
     for sgn, bound in ((1, info["bound_plus"]), (-1, info["bound_minus"])):
@@ -106,6 +124,7 @@ def test_lowmodes_8c4_residuals(method):
     assert np.abs(gram - np.eye(nev)).max() < 1e-12
     assert np.all(np.abs(nu) <= info["lam_next"] + 1e-12)
     assert np.all(np.diff(np.abs(nu)) >= -1e-14)
+    check_diagnostics(nu, rho, info)
 
 
 def test_lowmodes_free_field_degenerate():
@@ -124,6 +143,7 @@ def test_lowmodes_free_field_degenerate():
     pe = w[:, np.abs(np.abs(lam) - 0.6) < 1e-9]
     assert pe.shape[1] == 48
     assert np.linalg.norm(um.T @ um.conj() - pe @ pe.conj().T, 2) < 1e-9
+    check_diagnostics(nu, rho, info)
 
 
 @pytest.mark.parametrize("method", METHODS)
@@ -142,4 +162,7 @@ def test_dynamic_number_of_modes(dense4, method):
     l_expect = nev_min + int(np.argmax(ratios))
     assert info["nev_used"] == l_expect
     assert abs(info["lam_next"] - lam[l_expect]) < 1e-8
+    if l_expect < nev:
+        assert info["rho_next"] == rho[l_expect]
+    check_diagnostics(nu, rho, info)
 

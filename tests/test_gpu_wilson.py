@@ -42,6 +42,33 @@ def cu(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
 
 
+def f16_site_bound(nb_psi_norms, self_norm, out_norm):
+    """Per-site error bound of Q (or of the dslash) with F16 storage.
+
+    F16 spinors keep each real as a half of value / m (m the site's largest
+    |real|): error <= 2^-12 m per real, so <= sqrt(24) 2^-12 |psi(y)| ~ 1.2e-3 |psi(y)|
+    per site; F16 links (entries <= 1): |dU|_2 <= |dU|_F <= sqrt(18) 2^-12 ~ 1.04e-3.
+    Each hop U (1 -+ gamma) psi(y) has norm <= 2 |psi(y)| and enters with weight
+    1/2 (Q) or 1 (dslash); (4+m) = 2.6 weighs the site term; the output is
+    rounded once more (1.2e-3 |out(x)|).  With weight 2 for the dslash hops:
+        |err(x)| <= 2.5e-3 (sum_y |psi(y)| + 2.6 |psi(x)| + |out(x)|) * 2,
+    FP32 arithmetic (~1e-6) included in the margin.  A wrong link or neighbour
+    at a single site would exceed it by orders of magnitude."""
+    return 5e-3 * (nb_psi_norms + 2.6 * self_norm + out_norm)
+
+
+def f16_site_errors_ok(got, ref, psi, nb, self_term=True):
+    """Largest ratio of the per-site error to f16_site_bound; nb: [sites, 8]
+    indices into psi; self_term: Q (psi and the output on the same sites) or
+    the dslash (no same-site term)."""
+    pn = np.linalg.norm(psi.reshape(psi.shape[0], -1), axis=1)
+    nbn = pn[nb].sum(axis=1)
+    selfn = pn if self_term else 0.0
+    err = np.linalg.norm((got - ref).reshape(got.shape[0], -1), axis=1)
+    bound = f16_site_bound(nbn, selfn, np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1))
+    return float((err / bound).max())
+
+
 _CACHE = {}
 
 
@@ -114,6 +141,8 @@ def test_apply_Q_parity(dims, fmt):
     ndq.apply_Q(g, U, M, x, y)
     got = y.unpack().cpu().numpy()[0]
     assert rel_l2(got, ref) <= tol(sp, lp)
+    if ndq.F16 in (sp, lp):
+        assert f16_site_errors_ok(got, ref, psi, geometry.neighbour_table(dims)) <= 1.0
 
 
 @pytest.mark.parametrize("fmt", [(ndq.F64, ndq.F64, 18), (ndq.F64, ndq.F64, 12), (ndq.F32, ndq.F32, 18),
@@ -193,7 +222,10 @@ def test_apply_Q_full_size_16c32(fmt):
     x = ndq.SpinorField.pack(g, cu(psi), sp, ndq.FULL)
     y = x.like()
     ndq.apply_Q(g, U, M, x, y)
-    assert rel_l2(y.unpack().cpu().numpy()[0], ref) <= tol(sp, lp)
+    got = y.unpack().cpu().numpy()[0]
+    assert rel_l2(got, ref) <= tol(sp, lp)
+    if ndq.F16 in (sp, lp):
+        assert f16_site_errors_ok(got, ref, psi, geometry.neighbour_table(dims)) <= 1.0
 
 
 @pytest.mark.parametrize("block,xcd", [(0, 0), (64, 0), (128, 1), (256, 0), (256, 1)])
@@ -245,7 +277,11 @@ def test_dslash_full_size_16c32_every_shape(fmt, block, xcd, out_parity):
         ndq.apply_dslash(g, U, x, y)
     finally:
         ndq.set_launch(0, True)
-    assert rel_l2(y.unpack().cpu().numpy()[0], ref) <= tol(sp, lp)
+    got = y.unpack().cpu().numpy()[0]
+    assert rel_l2(got, ref) <= tol(sp, lp)
+    if ndq.F16 in (sp, lp):
+        nb = geometry.eo_neighbour_table(dims)[out_parity]
+        assert f16_site_errors_ok(got, ref, psi, nb, self_term=False) <= 1.0
 
 
 @pytest.mark.parametrize("fmt", [(ndq.F64, ndq.F64, 18), (ndq.F32, ndq.F32, 12), (ndq.F16, ndq.F16, 12)])

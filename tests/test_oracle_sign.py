@@ -238,3 +238,18 @@ def test_ritz_functional_free_field_degenerate(dense_cold):
     assert np.allclose(mu, 0.36, atol=1e-12)
     pe = dense_cold.W[:, np.abs(np.abs(dense_cold.lam) - 0.6) < 1e-9]
     assert np.linalg.norm(x.T - pe @ (pe.conj().T @ x.T)) < 1e-9
+
+
+@pytest.mark.parametrize("form", ["literal", "sandwich"])
+def test_projection_of_a_batch(dense_tiny, form):
+    """Each field of a batch is projected exactly as when passed alone."""
+    q = dense_tiny.Q
+    nu, modes = lowmodes.dense_lowmodes(q, 5, eig=(dense_tiny.lam, dense_tiny.W))
+    rng = np.random.default_rng(12)
+    batch = rng.normal(size=(3, q.shape[0])) + 1j * rng.normal(size=(3, q.shape[0]))
+    fn = sign.project_literal if form == "literal" else sign.project_sandwich
+    r = sign.dense_sign_approx(q, approx.zolotarev(0.1, 6), LMAX, eig=(dense_tiny.lam, dense_tiny.W))
+    got = fn(lambda t: t @ r.T, modes, nu, batch)
+    for j in range(3):
+        one = fn(lambda t: r @ t, modes, nu, batch[j])
+        assert np.abs(got[j] - one).max() < 1e-13
