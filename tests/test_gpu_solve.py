@@ -160,7 +160,7 @@ def test_production_lattice_apply_and_solves():
     k = (info["lam_next"] - info["rho_next"]) / LMAX
     ref_poly = _poly_for(k, 1e-4)
     ap64 = ndq.Approx.from_coeffs(ndq.MINMAX_POLY, ref_poly.c, lo=k * k, delta=ref_poly.delta)
-    ap_lo = ndq.Approx(ndq.MINMAX_POLY, k * k, max(8, ref_poly.n - 24))
+    ap_lo = ndq.Approx(ndq.MINMAX_POLY, k * k, max(8, len(ref_poly.c) - 1 - 24))
     ov64 = ndq.Overlap(g, M, ap64, LMAX, modes=modes, nu=nu, mq=MQ, form=ndq.ndq.SANDWICH)
     ov_lo = ndq.Overlap(g, M, ap_lo, LMAX, modes=modes, nu=nu, mq=MQ)
     psi = synthetic.spinor(v, seed=21)
