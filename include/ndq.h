@@ -241,6 +241,20 @@ int ndq_apply_DN(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params
                  const ndq_spinor* in, const ndq_spinor* out, void* ws, size_t ws_bytes,
                  ndq_stats* stats, void* stream);
 
+/* ndq_apply_DN for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same operation, kernels and results as ndq_apply_DN, with the workspace
+ * taken from a static device array of ndq_noalloc_scratch_bytes() (32 MiB)
+ * that each GPU holds from the first call on it until the process ends.  No
+ * allocating call is made.  The caller still owns in and out.  Every call on
+ * one GPU shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * p->graph must be 0.  Errors: those of ndq_apply_DN; NDQ_ENOMEM when
+ * ndq_workspace_bytes(g, p, in->prec, NDQ_OP_DN) exceeds the static size. */
+size_t ndq_noalloc_scratch_bytes(void);
+int ndq_apply_DN_noalloc(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p,
+                         const ndq_spinor* in, const ndq_spinor* out, ndq_stats* stats, void* stream);
+
 /* ---- solving D_N^m x = b --------------------------------------------------- */
 typedef struct {
     double tol;           /* target true residual |b - D x| / |b|, D the FP64 operator of p64 */

@@ -154,6 +154,9 @@ _SIG = {
                             ctypes.POINTER(_Spinor), _P, ctypes.c_size_t, ctypes.POINTER(_Stats), _P]),
     "ndq_apply_DN": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Params), ctypes.POINTER(_Spinor),
                           ctypes.POINTER(_Spinor), _P, ctypes.c_size_t, ctypes.POINTER(_Stats), _P]),
+    "ndq_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "ndq_apply_DN_noalloc": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Params), ctypes.POINTER(_Spinor),
+                                  ctypes.POINTER(_Spinor), ctypes.POINTER(_Stats), _P]),
     "ndq_lowmodes_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(_LmParams)]),
     "ndq_lowmodes_compute": (_I, [_P, ctypes.POINTER(_Gauge), _D, _D, ctypes.POINTER(_LmParams),
                                   ctypes.POINTER(_Spinor), _P, ctypes.POINTER(_D), ctypes.POINTER(_D),
@@ -462,6 +465,19 @@ def apply_DN(geom: Geometry, U: GaugeField, ov: Overlap, inp: SpinorField, out: 
     _check(lib().ndq_apply_DN(geom.handle, ctypes.byref(U.desc), ctypes.byref(ov.p), ctypes.byref(inp.desc),
                               ctypes.byref(out.desc), _ptr(ws), ws.numel(), ctypes.byref(st), _stream(stream)))
     return st.as_dict()
+
+
+def apply_DN_noalloc(geom: Geometry, U: GaugeField, ov: Overlap, inp: SpinorField, out: SpinorField,
+                     stream=None) -> dict:
+    """D_N^m inp with the library's static device scratch (no workspace argument)."""
+    st = _Stats()
+    _check(lib().ndq_apply_DN_noalloc(geom.handle, ctypes.byref(U.desc), ctypes.byref(ov.p), ctypes.byref(inp.desc),
+                                      ctypes.byref(out.desc), ctypes.byref(st), _stream(stream)))
+    return st.as_dict()
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().ndq_noalloc_scratch_bytes())
 
 
 def lowmodes_compute(geom: Geometry, U: GaugeField, m: float, lam_max: float, start: SpinorField, nev: int,
