@@ -62,8 +62,21 @@ def _csvs(d: str, suffix: str):
     return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
 
 
+def _dbs(d: str):
+    return sorted(glob.glob(os.path.join(d, "**", "*results.db"), recursive=True))
+
+
 def kernel_stats(trace_dir: str):
+    """Per-kernel calls and durations from a kernel-trace run (CSV statistics,
+    or the rocpd SQLite database that rocprofv3 writes by default)."""
     rows = []
+    for path in _dbs(trace_dir):
+        import sqlite3
+        con = sqlite3.connect(path)
+        q = "select name, count(*), avg(duration), min(duration), max(duration) from kernels group by name"
+        for name, n, avg, mn, mx in con.execute(q):
+            rows.append({"name": name, "calls": int(n), "avg_ns": float(avg), "min_ns": float(mn), "max_ns": float(mx)})
+        con.close()
     for path in _csvs(trace_dir, "kernel_stats.csv"):
         with open(path) as fh:
             for r in csv.DictReader(fh):
@@ -88,6 +101,13 @@ def stats_text(runs, command: str) -> str:
 def counters(pmc_dir: str, counter: str):
     """{kernel name: [per-dispatch value]} for one counter."""
     out = {}
+    for path in _dbs(pmc_dir):
+        import sqlite3
+        con = sqlite3.connect(path)
+        q = "select kernel_name, value from counters_collection where counter_name = ? order by dispatch_id"
+        for name, val in con.execute(q, (counter,)):
+            out.setdefault(name, []).append(float(val))
+        con.close()
     for path in _csvs(pmc_dir, "counter_collection.csv"):
         with open(path) as fh:
             for r in csv.DictReader(fh):
