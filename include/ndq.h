@@ -221,22 +221,32 @@ typedef struct {
 
 enum { NDQ_OP_SIGN = 0, NDQ_OP_DN = 1, NDQ_OP_SOLVE = 2 };
 
-/* Workspace (device bytes) that ndq_apply_sign / ndq_apply_DN / ndq_solve_DN need
- * for fields of precision `prec`.  0 on invalid arguments. */
+/* Workspace (device bytes) that ndq_apply_sign / ndq_apply_DN need for fields
+ * of precision `prec` with one right-hand side (ndq_workspace_bytes) or nrhs
+ * right-hand sides (ndq_workspace_bytes_nrhs, 1 <= nrhs <= 32).  0 on invalid
+ * arguments. */
 size_t ndq_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p, int prec, int op);
+size_t ndq_workspace_bytes_nrhs(const ndq_geom* g, const ndq_overlap_params* p, int prec, int op, int nrhs);
 
 /* out = sign(Q) in by Eq. 11: with c = U^H in and t = X r(X^2) in (the approximant
  * evaluated by Clenshaw's recurrence for the polynomial, by multi-shift CG for the
  * rational form), out = t + U (sign(nu) * c - U^H t); NDQ_SANDWICH applies the
- * approximant to (1 - P) in instead.  in, out: NDQ_FULL, nrhs 1, same precision
- * (arithmetic FP64 for F64 fields, FP32 otherwise; projections always FP64).
+ * approximant to (1 - P) in instead.  in, out: NDQ_FULL, same precision, the
+ * same number nrhs (1..32) of right-hand sides (arithmetic FP64 for F64 fields,
+ * FP32 otherwise; projections always FP64).  With nrhs > 1 and the polynomial
+ * approximant every stencil application of the recurrence serves all nrhs
+ * fields with one load of the links per tile, and the projections are block
+ * products with the modes on the matrix cores (results equal the one-field call
+ * up to the rounding of those sums); the rational approximant runs the fields
+ * one after the other.  Workspace: ndq_workspace_bytes_nrhs.
  * Synchronises `stream` for the rational approximant (convergence checks).
  * Errors: NDQ_ENOMEM (workspace), NDQ_ENOCONV (CG limit), NDQ_ENAN, NDQ_ESINGULAR (nu_k = 0). */
 int ndq_apply_sign(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p,
                    const ndq_spinor* in, const ndq_spinor* out, void* ws, size_t ws_bytes,
                    ndq_stats* stats, void* stream);
 
-/* out = D_N^m in = (1/abar - mq/2)(in + gamma5 sign(Q) in) + mq in  (Eq. 4, Eq. 12). */
+/* out = D_N^m in = (1/abar - mq/2)(in + gamma5 sign(Q) in) + mq in  (Eq. 4, Eq. 12),
+ * for every right-hand side of in (as ndq_apply_sign). */
 int ndq_apply_DN(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p,
                  const ndq_spinor* in, const ndq_spinor* out, void* ws, size_t ws_bytes,
                  ndq_stats* stats, void* stream);
@@ -270,6 +280,9 @@ typedef struct {
 
 size_t ndq_solve_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p64, const ndq_overlap_params* plo,
                                  const ndq_solve_params* sp);
+/* The same for a block of nrhs right-hand sides (1 <= nrhs <= 32). */
+size_t ndq_solve_workspace_bytes_nrhs(const ndq_geom* g, const ndq_overlap_params* p64, const ndq_overlap_params* plo,
+                                      const ndq_solve_params* sp, int nrhs);
 
 /* x = (D_N^m)^{-1} b (Eq. 4 with the massive form of Eq. 12).  FP64 defect
  * correction: r = b - D x with the FP64 operator (U64, p64); while |r| > tol |b|,
@@ -279,9 +292,17 @@ size_t ndq_solve_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p6
  * Both operators apply Eq. 11 in its sandwich form whatever p64->form and
  * p_lo->form say: CG on the normal equations needs D^H = gamma5 D gamma5, i.e. a
  * Hermitian sign(Q), which the literal form is only up to O(rho_k).
- * b, x: F64 NDQ_FULL, nrhs 1; x holds the initial guess on entry.  Synchronises
- * `stream`.  stats: outer steps, inner CG iterations, Q applications, final true
- * relative residual.  Errors: NDQ_ENOCONV, NDQ_ENOMEM, NDQ_ENAN, NDQ_EPREC. */
+ * b, x: F64 NDQ_FULL with the same nrhs (1..32); x holds the initial guess on
+ * entry.  With nrhs > 1 (CGNE) every field has its own defect correction and
+ * CGNE scalars, and all fields share each application of D: one call of the
+ * stencil per step serves the whole block (links loaded once per tile), which
+ * is the batched solve of many sources on one gauge field (e.g. the 12
+ * spin-colour point sources); a field that has converged keeps its solution
+ * while the others continue.  With sectors = 1 the fields are solved one after
+ * the other.  Workspace: ndq_solve_workspace_bytes_nrhs.  Synchronises
+ * `stream`.  stats: outer steps, inner CG iterations (block iterations for
+ * nrhs > 1), Q applications, final true relative residual (the largest over the
+ * fields).  Errors: NDQ_ENOCONV, NDQ_ENOMEM, NDQ_ENAN, NDQ_EPREC. */
 int ndq_solve_DN(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* U_lo, const ndq_overlap_params* p64,
                  const ndq_overlap_params* p_lo, const ndq_solve_params* sp, const ndq_spinor* b,
                  const ndq_spinor* x, void* ws, size_t ws_bytes, ndq_stats* stats, void* stream);

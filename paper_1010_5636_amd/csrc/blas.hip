@@ -23,19 +23,26 @@ constexpr int kBlock = 256;
 __device__ __forceinline__ double coefv(const Coef& c) { return c.d ? c.f * (*c.d) : c.f; }
 
 struct LinArgs {
-    SpinorView out;
+    SpinorView out;            // right-hand side r at base + r * rhs_bytes (every view)
     SpinorView v[4];
     Coef c[4];
     int g5[4];
     int nv;
     int32_t nsites;
-    double* partials;
+    double* partials;          // per (right-hand side, block): partials[r * gridDim.x + block]
 };
 
+// Coefficients that differ between right-hand sides: c[j][r] for vector j.
+struct LinRhs {
+    double c[4][NDQ_MAX_BATCH];
+};
+
+// One site of out_r = sum_j c_j G5^{g5_j} v_j,r (grid row y = right-hand side r).
 template <int P>
-__global__ void __launch_bounds__(kBlock) k_lincomb(LinArgs a) {
+__device__ __forceinline__ void lincomb_site(const LinArgs& a, const double* cr) {
     using R = typename SpinorIO<P>::R;
     __shared__ double lds[kBlock / 64];
+    const int r = blockIdx.y;
     const int32_t s = blockIdx.x * kBlock + threadIdx.x;
     double red = 0.0;
     if (s < a.nsites) {
@@ -44,45 +51,64 @@ __global__ void __launch_bounds__(kBlock) k_lincomb(LinArgs a) {
         for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
         for (int j = 0; j < a.nv; ++j) {
             C<R> x[12];
-            SpinorIO<P>::load(a.v[j], s, x);
-            const R c = (R)coefv(a.c[j]);
+            SpinorView vj = a.v[j];
+            vj.base += (int64_t)r * vj.rhs_bytes;
+            SpinorIO<P>::load(vj, s, x);
+            const R c = (R)(cr ? cr[j * NDQ_MAX_BATCH + r] : coefv(a.c[j]));
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 const R ck = (a.g5[j] && k >= 6) ? -c : c;
                 acc[k] = {acc[k].r + ck * x[k].r, acc[k].i + ck * x[k].i};
             }
         }
-        SpinorIO<P>::store(a.out, s, acc);
+        SpinorView vo = a.out;
+        vo.base += (int64_t)r * vo.rhs_bytes;
+        SpinorIO<P>::store(vo, s, acc);
         if (a.partials) {
-            if constexpr (P == P16) SpinorIO<P>::load(a.out, s, acc);
+            if constexpr (P == P16) SpinorIO<P>::load(vo, s, acc);
 #pragma unroll
             for (int k = 0; k < 12; ++k) red += (double)acc[k].r * acc[k].r + (double)acc[k].i * acc[k].i;
         }
     }
     if (a.partials) {
         const double t = block_sum(red, lds);
-        if (threadIdx.x == 0) a.partials[blockIdx.x] = t;
+        if (threadIdx.x == 0) a.partials[(int64_t)r * gridDim.x + blockIdx.x] = t;
     }
 }
 
-// dst[j] = sum_b partials[b * nvals + j], blocks added in index order.
-__global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partials, int nblocks, int nvals,
-                                                   double* __restrict__ dst) {
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_lincomb(LinArgs a) {
+    lincomb_site<P>(a, nullptr);
+}
+
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_lincomb_rhs(LinArgs a, LinRhs b) {
+    lincomb_site<P>(a, &b.c[0][0]);
+}
+
+// dst[j] = sum_b partials[j * jstride + b * bstride] for j < gridDim.x, one
+// workgroup per value; every value adds its blocks in the same fixed order.
+__global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partials, int nblocks, int64_t jstride,
+                                                   int bstride, double* __restrict__ dst) {
     __shared__ double lds[kBlock / 64];
-    for (int j = 0; j < nvals; ++j) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partials[(int64_t)b * nvals + j];
-        s = block_sum(s, lds);
-        if (threadIdx.x == 0) dst[j] = s;
-        __syncthreads();
-    }
+    const int j = blockIdx.x;
+    const double* p = partials + (int64_t)j * jstride;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) s += p[(int64_t)b * bstride];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) dst[j] = s;
 }
 
+// Per right-hand side r (grid row y): <x_r, y_r> (complex) or |x_r|^2 into
+// partials[(nv * r + c) * gridDim.x + block], nv = 2 or 1 values per field.
 template <int P>
 __global__ void __launch_bounds__(kBlock) k_dot(SpinorView x, SpinorView y, int has_y, int32_t n,
                                                 double* __restrict__ partials) {
     using R = typename SpinorIO<P>::R;
     __shared__ double lds[kBlock / 64];
+    const int r = blockIdx.y;
+    x.base += (int64_t)r * x.rhs_bytes;
+    y.base += (int64_t)r * y.rhs_bytes;
     const int32_t s = blockIdx.x * kBlock + threadIdx.x;
     double re = 0.0, im = 0.0;
     if (s < n) {
@@ -101,16 +127,17 @@ __global__ void __launch_bounds__(kBlock) k_dot(SpinorView x, SpinorView y, int 
             for (int k = 0; k < 12; ++k) re += (double)a[k].r * a[k].r + (double)a[k].i * a[k].i;
         }
     }
+    const int64_t nb = gridDim.x;
     const double sr = block_sum(re, lds);
     __syncthreads();
     if (has_y) {
         const double si = block_sum(im, lds);
         if (threadIdx.x == 0) {
-            partials[2 * blockIdx.x] = sr;
-            partials[2 * blockIdx.x + 1] = si;
+            partials[(2 * r) * nb + blockIdx.x] = sr;
+            partials[(2 * r + 1) * nb + blockIdx.x] = si;
         }
     } else if (threadIdx.x == 0) {
-        partials[blockIdx.x] = sr;
+        partials[r * nb + blockIdx.x] = sr;
     }
 }
 
@@ -118,6 +145,8 @@ template <int PD, int PS>
 __global__ void __launch_bounds__(kBlock) k_convert(SpinorView dst, SpinorView src, int32_t n) {
     const int32_t s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
+    dst.base += (int64_t)blockIdx.y * dst.rhs_bytes;
+    src.base += (int64_t)blockIdx.y * src.rhs_bytes;
     using RS = typename SpinorIO<PS>::R;
     using RD = typename SpinorIO<PD>::R;
     C<RS> a[12];
@@ -451,8 +480,22 @@ __global__ void __launch_bounds__(kBlock) k_phase_copy(SpinorView src, SpinorVie
 // fixed order by k_gram_reduce.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// Component c of field `base` (precision PB, full-field layout with plane stride V) in FP64.
+template <int PB>
+__device__ __forceinline__ double2 field_comp(const char* base, int32_t V, int c, int32_t site) {
+    SpinorView v;
+    v.base = const_cast<char*>(base);
+    v.stride = V;
+    v.site0 = 0;
+    v.rhs_bytes = 0;
+    const auto x = SpinorIO<PB>::load_comp(v, site, c);
+    return make_double2((double)x.r, (double)x.i);
+}
+
+// B may be F64, F32 or F16 (PB; converted to FP64 on load); A is FP64.
+template <int PB>
 __global__ void __launch_bounds__(256) k_gram(const char* __restrict__ A, int na, const char* __restrict__ B, int nb,
-                                              int64_t vb, int32_t V, int32_t sites_per_wave, int nwaves,
+                                              int64_t vb, int64_t vbB, int32_t V, int32_t sites_per_wave, int nwaves,
                                               double* __restrict__ partials) {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -484,7 +527,7 @@ __global__ void __launch_bounds__(256) k_gram(const char* __restrict__ A, int na
                 if (q < ntj) {
                     const int jb = q * 16 + t;
                     double2 b = make_double2(0.0, 0.0);
-                    if (jb < nb && vs) b = reinterpret_cast<const double2*>(B + (int64_t)jb * vb)[plane + site];
+                    if (jb < nb && vs) b = field_comp<PB>(B + (int64_t)jb * vbB, V, c, site);
                     re[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re[q], 0, 0, 0);
                     re[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, re[q], 0, 0, 0);
                     im[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im[q], 0, 0, 0);
@@ -525,6 +568,66 @@ __global__ void __launch_bounds__(kBlock) k_gram_reduce(const double* __restrict
     G[2 * e + 1] = si;
 }
 
+// Projection coefficients of a block of R fields: coef[k][r] = sc * (use_sign ?
+// sign_k : 1) * c[k][r] + sd * d[k][r] (complex, row-major nev x R; d may be null).
+__global__ void k_mode_coef_block(const double* c, const double* d, ModeSigns sg, int use_sign, int nev, int nr,
+                                  double sc, double sd, double* coef) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nev * nr) return;
+    const int k = e / nr;
+    const double f = sc * (use_sign ? (double)sg.s[k] : 1.0);
+    coef[2 * e] = f * c[2 * e] + (d ? sd * d[2 * e] : 0.0);
+    coef[2 * e + 1] = f * c[2 * e + 1] + (d ? sd * d[2 * e + 1] : 0.0);
+}
+
+// out_r = in_r + sum_k coef[k][r] u_k for a block of fields (r < nr), one lane
+// per (complex component c, site s) with sites fastest, so that every load is
+// a contiguous run of one plane; grid row y takes the fields r = kRotJ y ..
+// kRotJ y + kRotJ - 1, which read each mode plane once between them.  The sum
+// runs in the order of k_mode_update (start from in, add the modes in index
+// order, FP64).  PI: precision of `in` (F64, F32 or F16); PO: precision of
+// `out` (F64 or F32; an F16 result goes through an F32 block and k_convert,
+// which rounds exactly as k_mode_update<P16> does).
+template <int PI, int PO>
+__global__ void __launch_bounds__(kBlock) k_mode_update_block(const char* __restrict__ modes, int64_t mode_bytes,
+                                                              int nev, const double* __restrict__ coef, int nr,
+                                                              SpinorView in, SpinorView out, int32_t n) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= 12 * (int64_t)n) return;
+    const int c = (int)(t / n);
+    const int32_t s = (int32_t)(t - (int64_t)c * n);
+    const int r0 = kRotJ * blockIdx.y;
+    const int cnt = min(kRotJ, nr - r0);
+    C<double> acc[kRotJ];
+#pragma unroll
+    for (int j = 0; j < kRotJ; ++j) {
+        if (j < cnt) {
+            SpinorView v = in;
+            v.base += (int64_t)(r0 + j) * in.rhs_bytes;
+            const auto x = SpinorIO<PI>::load_comp(v, s, c);
+            acc[j] = {(double)x.r, (double)x.i};
+        } else {
+            acc[j] = {0.0, 0.0};
+        }
+    }
+    for (int k = 0; k < nev; ++k) {
+        const double2 w = reinterpret_cast<const double2*>(modes + (int64_t)k * mode_bytes)[(int64_t)c * n + s];
+        const double* ck = coef + 2 * ((int64_t)k * nr + r0);
+#pragma unroll
+        for (int j = 0; j < kRotJ; ++j)
+            if (j < cnt) acc[j] = cfma(acc[j], C<double>{ck[2 * j], ck[2 * j + 1]}, C<double>{w.x, w.y});
+    }
+    using RO = typename SpinorIO<PO>::R;
+#pragma unroll
+    for (int j = 0; j < kRotJ; ++j) {
+        if (j < cnt) {
+            SpinorView o = out;
+            o.base += (int64_t)(r0 + j) * out.rhs_bytes;
+            SpinorIO<PO>::store_comp(o, s, c, C<RO>{(RO)acc[j].r, (RO)acc[j].i});
+        }
+    }
+}
+
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -538,20 +641,31 @@ size_t partials_capacity(const ndq_geom* g, int nvals) {
     return (size_t)blocks * (size_t)std::max(nvals, 1) * sizeof(double);
 }
 
-int lincomb(const ndq_geom* g, int prec, const ndq_spinor* out, int nv, const ndq_spinor* const* v, const Coef* c,
-            const int* g5, double* partials, hipStream_t st) {
-    LinArgs a;
+namespace {
+int lin_setup(const ndq_geom* g, const ndq_spinor* out, int nv, const ndq_spinor* const* v, const Coef* c,
+              const int* g5, double* partials, LinArgs& a) {
     memset(&a, 0, sizeof(a));
+    const int nr = out->nrhs;
     a.out = flat_view(g, out);
     a.nv = nv;
     for (int j = 0; j < nv; ++j) {
+        if (v[j]->nrhs != nr) return fail(NDQ_EINVAL, "lincomb: operand %d has %d fields, the output %d", j, v[j]->nrhs, nr);
         a.v[j] = flat_view(g, v[j]);
-        a.c[j] = c[j];
+        if (c) a.c[j] = c[j];
         a.g5[j] = g5 ? g5[j] : 0;
     }
     a.nsites = (int32_t)g->volume;
     a.partials = partials;
-    const dim3 grid(nblocks(g->volume));
+    return NDQ_OK;
+}
+}  // namespace
+
+int lincomb(const ndq_geom* g, int prec, const ndq_spinor* out, int nv, const ndq_spinor* const* v, const Coef* c,
+            const int* g5, double* partials, hipStream_t st) {
+    LinArgs a;
+    int rc = lin_setup(g, out, nv, v, c, g5, partials, a);
+    if (rc) return rc;
+    const dim3 grid(nblocks(g->volume), out->nrhs);
     switch (prec) {
         case NDQ_F64: hipLaunchKernelGGL(k_lincomb<P64>, grid, dim3(kBlock), 0, st, a); break;
         case NDQ_F32: hipLaunchKernelGGL(k_lincomb<P32>, grid, dim3(kBlock), 0, st, a); break;
@@ -561,17 +675,44 @@ int lincomb(const ndq_geom* g, int prec, const ndq_spinor* out, int nv, const nd
     return NDQ_OK;
 }
 
+int lincomb_rhs(const ndq_geom* g, int prec, const ndq_spinor* out, int nv, const ndq_spinor* const* v,
+                const double* cr, const int* g5, double* partials, hipStream_t st) {
+    if (out->nrhs > NDQ_MAX_BATCH) return fail(NDQ_EINVAL, "lincomb: at most %d fields per block", NDQ_MAX_BATCH);
+    LinArgs a;
+    int rc = lin_setup(g, out, nv, v, nullptr, g5, partials, a);
+    if (rc) return rc;
+    LinRhs b;
+    memset(&b, 0, sizeof(b));
+    for (int j = 0; j < nv; ++j)
+        for (int r = 0; r < out->nrhs; ++r) b.c[j][r] = cr[j * out->nrhs + r];
+    const dim3 grid(nblocks(g->volume), out->nrhs);
+    switch (prec) {
+        case NDQ_F64: hipLaunchKernelGGL(k_lincomb_rhs<P64>, grid, dim3(kBlock), 0, st, a, b); break;
+        case NDQ_F32: hipLaunchKernelGGL(k_lincomb_rhs<P32>, grid, dim3(kBlock), 0, st, a, b); break;
+        default: hipLaunchKernelGGL(k_lincomb_rhs<P16>, grid, dim3(kBlock), 0, st, a, b); break;
+    }
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
 int reduce_partials(const double* partials, int nb, int nvals, double* dst, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, partials, nb, nvals, dst);
+    hipLaunchKernelGGL(k_reduce, dim3(nvals), dim3(kBlock), 0, st, partials, nb, (int64_t)1, nvals, dst);
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int reduce_rows(const double* partials, int nb, int nvals, double* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(nvals), dim3(kBlock), 0, st, partials, nb, (int64_t)nb, 1, dst);
     NDQ_HIP(hipGetLastError());
     return NDQ_OK;
 }
 
 int dot(const ndq_geom* g, const ndq_spinor* x, const ndq_spinor* y, double* partials, double* dst, hipStream_t st) {
+    if (y && y->nrhs != x->nrhs) return fail(NDQ_EINVAL, "dot: operands with %d and %d fields", x->nrhs, y->nrhs);
     const SpinorView xv = flat_view(g, x);
     const SpinorView yv = y ? flat_view(g, y) : xv;
     const int32_t n = (int32_t)g->volume;
-    const dim3 grid(nblocks(n));
+    const dim3 grid(nblocks(n), x->nrhs);
     const int hy = y != nullptr;
     switch (x->prec) {
         case NDQ_F64: hipLaunchKernelGGL(k_dot<P64>, grid, dim3(kBlock), 0, st, xv, yv, hy, n, partials); break;
@@ -579,13 +720,14 @@ int dot(const ndq_geom* g, const ndq_spinor* x, const ndq_spinor* y, double* par
         default: hipLaunchKernelGGL(k_dot<P16>, grid, dim3(kBlock), 0, st, xv, yv, hy, n, partials); break;
     }
     NDQ_HIP(hipGetLastError());
-    return reduce_partials(partials, (int)grid.x, hy ? 2 : 1, dst, st);
+    return reduce_rows(partials, (int)grid.x, (hy ? 2 : 1) * x->nrhs, dst, st);
 }
 
 int convert(const ndq_geom* g, const ndq_spinor* dst, const ndq_spinor* src, hipStream_t st) {
+    if (dst->nrhs != src->nrhs) return fail(NDQ_EINVAL, "convert: %d fields into %d", src->nrhs, dst->nrhs);
     const SpinorView d = flat_view(g, dst), s = flat_view(g, src);
     const int32_t n = (int32_t)g->volume;
-    const dim3 grid(nblocks(n));
+    const dim3 grid(nblocks(n), dst->nrhs);
     const int key = dst->prec * 3 + src->prec;
     switch (key) {
         case NDQ_F64 * 3 + NDQ_F64: hipLaunchKernelGGL((k_convert<P64, P64>), grid, dim3(kBlock), 0, st, d, s, n); break;
@@ -623,8 +765,8 @@ int gram(const ndq_geom* g, const void* A, int na, const void* B, int nb, double
     spw = (spw + 3) & ~3;
     const int64_t vb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
     const dim3 grid((unsigned)((nw + 3) / 4), (unsigned)((na + 15) / 16));
-    hipLaunchKernelGGL(k_gram, grid, dim3(256), 0, st, static_cast<const char*>(A), na, static_cast<const char*>(B),
-                       nb, vb, (int32_t)V, spw, nw, partials);
+    hipLaunchKernelGGL(k_gram<P64>, grid, dim3(256), 0, st, static_cast<const char*>(A), na, static_cast<const char*>(B),
+                       nb, vb, vb, (int32_t)V, spw, nw, partials);
     NDQ_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks((int64_t)na * nb)), dim3(kBlock), 0, st, partials, na, nb, nw, G);
     NDQ_HIP(hipGetLastError());
@@ -671,6 +813,60 @@ int mode_update(const ndq_geom* g, const void* modes, int nev, const double* coe
 int mode_coef(const double* c, const double* d, const ModeSigns& sg, int use_sign, int nev, double sc, double sd,
               double* coef, hipStream_t st) {
     hipLaunchKernelGGL(k_mode_coef, dim3(1), dim3(NDQ_MAX_MODES), 0, st, c, d, sg, use_sign, nev, sc, sd, coef);
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int gram_block(const ndq_geom* g, const void* A, int na, const ndq_spinor* B, double* partials, double* G,
+               hipStream_t st) {
+    const int nb = B->nrhs;
+    if (na < 1 || nb < 1 || na > 64 || nb > 64) return fail(NDQ_EINVAL, "gram: block sizes must be in [1, 64]");
+    const int nw = gram_waves(g);
+    const int64_t V = g->volume;
+    int32_t spw = (int32_t)((V + nw - 1) / nw);
+    spw = (spw + 3) & ~3;
+    const int64_t vb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
+    const int64_t vbB = spinor_rhs_bytes(g, B->prec, NDQ_FULL);
+    const dim3 grid((unsigned)((nw + 3) / 4), (unsigned)((na + 15) / 16));
+    const char* a = static_cast<const char*>(A);
+    const char* b = static_cast<const char*>(B->data);
+    switch (B->prec) {
+        case NDQ_F64: hipLaunchKernelGGL(k_gram<P64>, grid, dim3(256), 0, st, a, na, b, nb, vb, vbB, (int32_t)V, spw, nw, partials); break;
+        case NDQ_F32: hipLaunchKernelGGL(k_gram<P32>, grid, dim3(256), 0, st, a, na, b, nb, vb, vbB, (int32_t)V, spw, nw, partials); break;
+        default: hipLaunchKernelGGL(k_gram<P16>, grid, dim3(256), 0, st, a, na, b, nb, vb, vbB, (int32_t)V, spw, nw, partials); break;
+    }
+    NDQ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks((int64_t)na * nb)), dim3(kBlock), 0, st, partials, na, nb, nw, G);
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int mode_coef_block(const double* c, const double* d, const ModeSigns& sg, int use_sign, int nev, int nr, double sc,
+                    double sd, double* coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_mode_coef_block, dim3(nblocks((int64_t)nev * nr)), dim3(kBlock), 0, st, c, d, sg, use_sign,
+                       nev, nr, sc, sd, coef);
+    NDQ_HIP(hipGetLastError());
+    return NDQ_OK;
+}
+
+int mode_update_block(const ndq_geom* g, const void* modes, int nev, const double* coef, const ndq_spinor* in,
+                      const ndq_spinor* out, hipStream_t st) {
+    const int nr = in->nrhs;
+    if (out->nrhs != nr) return fail(NDQ_EINVAL, "mode update: %d fields into %d", nr, out->nrhs);
+    if (out->prec == NDQ_F16) return fail(NDQ_EPREC, "mode update: the block form writes F64 or F32 fields");
+    const SpinorView iv = flat_view(g, in), ov = flat_view(g, out);
+    const int64_t mb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
+    const char* mp = static_cast<const char*>(modes);
+    const int64_t lanes = 12 * (int64_t)g->volume;
+    const dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock), (unsigned)((nr + kRotJ - 1) / kRotJ));
+    const int32_t n = (int32_t)g->volume;
+    const int key = in->prec * 3 + out->prec;
+    switch (key) {
+        case NDQ_F64 * 3 + NDQ_F64: hipLaunchKernelGGL((k_mode_update_block<P64, P64>), grid, dim3(kBlock), 0, st, mp, mb, nev, coef, nr, iv, ov, n); break;
+        case NDQ_F32 * 3 + NDQ_F32: hipLaunchKernelGGL((k_mode_update_block<P32, P32>), grid, dim3(kBlock), 0, st, mp, mb, nev, coef, nr, iv, ov, n); break;
+        case NDQ_F16 * 3 + NDQ_F32: hipLaunchKernelGGL((k_mode_update_block<P16, P32>), grid, dim3(kBlock), 0, st, mp, mb, nev, coef, nr, iv, ov, n); break;
+        default: return fail(NDQ_EPREC, "mode update: unsupported precision pair (%d -> %d)", in->prec, out->prec);
+    }
     NDQ_HIP(hipGetLastError());
     return NDQ_OK;
 }

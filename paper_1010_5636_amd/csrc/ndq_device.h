@@ -214,6 +214,13 @@ template <> struct SpinorIO<P16> {
         }
         reinterpret_cast<float*>(v.base + (int64_t)48 * v.stride)[s] = amax;
     }
+    // single complex component c: half2 (c & 3) of plane c >> 2, times the site's scale
+    __device__ static __forceinline__ C<R> load_comp(const SpinorView& v, int64_t s, int c) {
+        const uint32_t w = reinterpret_cast<const uint32_t*>(v.base)[4 * ((int64_t)(c >> 2) * v.stride + s) + (c & 3)];
+        const float scale = reinterpret_cast<const float*>(v.base + (int64_t)48 * v.stride)[s];
+        const float2 f = __half22float2(*reinterpret_cast<const __half2*>(&w));
+        return {f.x * scale, f.y * scale};
+    }
 };
 
 // ---------------------------------------------------------------------------

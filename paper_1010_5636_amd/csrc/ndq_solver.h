@@ -10,6 +10,7 @@
 
 #define NDQ_MAX_SHIFTS 32
 #define NDQ_MAX_MODES 64
+#define NDQ_MAX_BATCH 32   // right-hand sides of one batched sign, D_N or solve call
 
 namespace ndq {
 
@@ -50,6 +51,24 @@ inline ndq_spinor ws_spinor(Arena& ar, const ndq_geom* g, int prec) {
     return s;
 }
 
+// A block of nr full spinors of one precision in workspace memory.
+inline ndq_spinor ws_block(Arena& ar, const ndq_geom* g, int prec, int nr) {
+    ndq_spinor s;
+    s.data = ar.take((size_t)spinor_rhs_bytes(g, prec, NDQ_FULL) * nr);
+    s.prec = prec;
+    s.parity = NDQ_FULL;
+    s.nrhs = nr;
+    return s;
+}
+
+// Field r of a block, as a one-field descriptor.
+inline ndq_spinor rhs_slice(const ndq_geom* g, const ndq_spinor* s, int r) {
+    ndq_spinor o = *s;
+    o.data = static_cast<char*>(s->data) + spinor_rhs_bytes(g, s->prec, s->parity) * r;
+    o.nrhs = 1;
+    return o;
+}
+
 // View of a whole full spinor as V consecutive sites (for site-local kernels).
 inline SpinorView flat_view(const ndq_geom* g, const ndq_spinor* s, int rhs = 0) {
     SpinorView v = view_of(g, s, 0, rhs);
@@ -63,15 +82,25 @@ inline SpinorView flat_view(const ndq_geom* g, const ndq_spinor* s, int rhs = 0)
 size_t partials_capacity(const ndq_geom* g, int nvals);
 
 // out = sum_k c_k G5^{g5_k} v_k (k < nv <= 4), optional |out|^2 partials.
-// All vectors full fields of precision `prec`; out may alias a v_k.
+// All vectors full fields of precision `prec`; out may alias a v_k.  Every
+// operand holds out->nrhs fields; field r of out combines fields r of the v_k
+// (partials: per field and block, field-major, one value each).
 int lincomb(const ndq_geom* g, int prec, const ndq_spinor* out, int nv, const ndq_spinor* const* v,
             const Coef* c, const int* g5, double* partials, hipStream_t st);
-// Sum per-block partials into dst (nvals interleaved values per block).
+// The same with coefficients per field: cr[k * out->nrhs + r] for vector k and
+// field r (host array; out->nrhs <= NDQ_MAX_BATCH).
+int lincomb_rhs(const ndq_geom* g, int prec, const ndq_spinor* out, int nv, const ndq_spinor* const* v,
+                const double* cr, const int* g5, double* partials, hipStream_t st);
+// Sum per-block partials into dst: nvals values interleaved per block
+// (reduce_partials) or one row of nblocks partials per value (reduce_rows).
 int reduce_partials(const double* partials, int nblocks, int nvals, double* dst, hipStream_t st);
+int reduce_rows(const double* partials, int nblocks, int nvals, double* dst, hipStream_t st);
 int lincomb_blocks(const ndq_geom* g);
-// <x, y> (complex, FP64 accumulation) into dst[0..1]; |x|^2 into dst if y == nullptr.
+// <x_r, y_r> (complex, FP64 accumulation) into dst[2r..2r+1] for every field r
+// of the blocks x and y; |x_r|^2 into dst[r] if y == nullptr.  partials needs
+// partials_capacity(g, 2 * x->nrhs).
 int dot(const ndq_geom* g, const ndq_spinor* x, const ndq_spinor* y, double* partials, double* dst, hipStream_t st);
-// Precision conversion between full fields (same site layout).
+// Precision conversion between blocks of full fields (same site layout and count).
 int convert(const ndq_geom* g, const ndq_spinor* dst, const ndq_spinor* src, hipStream_t st);
 
 // Low modes: dots[k] = <u_k, v> for the nev packed F64 full spinors at `modes`.
@@ -87,6 +116,16 @@ int mode_dots(const ndq_geom* g, const void* modes, int nev, const ndq_spinor* v
 struct ModeSigns {
     float s[NDQ_MAX_MODES];
 };
+// Block forms for a block B of nr fields (any precision): G[k][r] = <u_k, B_r>
+// (nev x nr complex, row-major) on the matrix cores (partials:
+// gram_partials_bytes(g, nev, nr)); coef[k][r] as mode_coef; out_r = in_r +
+// sum_k coef[k][r] u_k (out F64 or F32; in F64, F32 or F16).
+int gram_block(const ndq_geom* g, const void* modes, int nev, const ndq_spinor* B, double* partials, double* G,
+               hipStream_t st);
+int mode_coef_block(const double* c, const double* d, const ModeSigns& sg, int use_sign, int nev, int nr, double sc,
+                    double sd, double* coef, hipStream_t st);
+int mode_update_block(const ndq_geom* g, const void* modes, int nev, const double* coef, const ndq_spinor* in,
+                      const ndq_spinor* out, hipStream_t st);
 int mode_coef(const double* c, const double* d, const ModeSigns& sg, int use_sign, int nev, double sc, double sd,
               double* coef, hipStream_t st);
 // out = in + sum_k coef_k u_k (coef complex, device array of 2*nev doubles).
@@ -142,7 +181,7 @@ inline ndq_overlap_params hermitian_form(const ndq_overlap_params* p) {
     return q;
 }
 
-size_t sign_workspace(const ndq_geom* g, const ndq_overlap_params* p, int prec);
+size_t sign_workspace(const ndq_geom* g, const ndq_overlap_params* p, int prec, int nr = 1);
 int apply_sign(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p, const ndq_spinor* in,
                const ndq_spinor* out, Arena& ar, ndq_stats* stats, hipStream_t st);
 

@@ -82,36 +82,47 @@ struct Scratch {
     MsState* ms;
 };
 
-Scratch take_scratch(Arena& ar, const ndq_geom* g, int nev) {
+Scratch take_scratch(Arena& ar, const ndq_geom* g, int nev, int nr = 1) {
     Scratch s;
-    const size_t pc = partials_capacity(g, std::max(2 * nev, 2));
+    size_t pc = partials_capacity(g, std::max(2 * nev, 2));
+    if (nr > 1 && nev > 0) pc = std::max(pc, gram_partials_bytes(g, nev, nr));
     s.partials = static_cast<double*>(ar.take(pc));
     s.part_tt = static_cast<double*>(ar.take(partials_capacity(g, 1)));
     s.part_rr = static_cast<double*>(ar.take(partials_capacity(g, 1)));
     s.part_pp = static_cast<double*>(ar.take(partials_capacity(g, 1)));
-    s.dots_c = static_cast<double*>(ar.take(2 * NDQ_MAX_MODES * sizeof(double)));
-    s.dots_d = static_cast<double*>(ar.take(2 * NDQ_MAX_MODES * sizeof(double)));
-    s.coef = static_cast<double*>(ar.take(2 * NDQ_MAX_MODES * sizeof(double)));
+    s.dots_c = static_cast<double*>(ar.take(2 * NDQ_MAX_MODES * nr * sizeof(double)));
+    s.dots_d = static_cast<double*>(ar.take(2 * NDQ_MAX_MODES * nr * sizeof(double)));
+    s.coef = static_cast<double*>(ar.take(2 * NDQ_MAX_MODES * nr * sizeof(double)));
     s.ms = static_cast<MsState*>(ar.take(sizeof(MsState)));
     return s;
 }
 
 Coef host(double v) { return Coef{v, nullptr}; }
 
-// out = X P(X^2) src, Clenshaw's recurrence.  Work vectors: B0, B1, T.
+// out = c0 Q in + sum_k cv_k v_k: the one-lane-per-site stencil for one field,
+// the multi-right-hand-side stencil (links loaded once per tile) for a block.
+int q_any(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in, const ndq_spinor* out, Coef c0,
+          int nv, const ndq_spinor* const* v, const Coef* cv, hipStream_t st) {
+    if (in->nrhs == 1) return q_combo(g, U, m, in, out, c0, nv, v, cv, nullptr, st);
+    return q_combo_block(g, U, m, in, out, c0, nv, v, cv, st);
+}
+
+// out = X P(X^2) src, Clenshaw's recurrence, for every field of the block src.
+// Work blocks: B0, B1, T.
 int poly_apply(const ndq_geom* g, const ndq_gauge* U, double m, const Approx& ap, double lam,
                const ndq_spinor* src, const ndq_spinor* out, Arena& ar, int64_t* qcount, hipStream_t st) {
     const int prec = src->prec;
+    const int nr = src->nrhs;
     const int n = ap.n;
     const double eps = ap.lo;
     const double za = 4.0 / ((1.0 - eps) * lam * lam);     // coefficient of Q Q b in 2 Z b
     const double zb = -2.0 * (1.0 + eps) / (1.0 - eps);    // coefficient of b in 2 Z b
     if (n == 0) {
-        *qcount += 1;
-        return q_combo(g, U, m, src, out, host(ap.a[0] / lam), 0, nullptr, nullptr, nullptr, st);
+        *qcount += nr;
+        return q_any(g, U, m, src, out, host(ap.a[0] / lam), 0, nullptr, nullptr, st);
     }
-    ndq_spinor B[2] = {ws_spinor(ar, g, prec), ws_spinor(ar, g, prec)};
-    ndq_spinor T = ws_spinor(ar, g, prec);
+    ndq_spinor B[2] = {ws_block(ar, g, prec, nr), ws_block(ar, g, prec, nr)};
+    ndq_spinor T = ws_block(ar, g, prec, nr);
     if (ar.overflow) return fail(NDQ_ENOMEM, "sign (polynomial): workspace too small (need %zu bytes)", ar.used);
     int rc;
     // b_n = c_n src
@@ -123,27 +134,27 @@ int poly_apply(const ndq_geom* g, const ndq_gauge* U, double m, const Approx& ap
     const ndq_spinor* b1 = &B[0];      // b_{j+1}
     const ndq_spinor* b2 = nullptr;    // b_{j+2} (zero at the start)
     for (int j = n - 1; j >= 1; --j) {
-        if ((rc = q_combo(g, U, m, b1, &T, host(1.0), 0, nullptr, nullptr, nullptr, st))) return rc;
+        if ((rc = q_any(g, U, m, b1, &T, host(1.0), 0, nullptr, nullptr, st))) return rc;
         const ndq_spinor* target = b2 ? b2 : &B[1];
         const ndq_spinor* v[3] = {src, b1, b2};
         const Coef c[3] = {host(ap.a[j]), host(zb), host(-1.0)};
-        if ((rc = q_combo(g, U, m, &T, target, host(za), b2 ? 3 : 2, v, c, nullptr, st))) return rc;
+        if ((rc = q_any(g, U, m, &T, target, host(za), b2 ? 3 : 2, v, c, st))) return rc;
         b2 = b1;
         b1 = target;
-        *qcount += 2;
+        *qcount += 2 * nr;
     }
     // P src = c_0 src + Z b_1 - b_2
-    if ((rc = q_combo(g, U, m, b1, &T, host(1.0), 0, nullptr, nullptr, nullptr, st))) return rc;
+    if ((rc = q_any(g, U, m, b1, &T, host(1.0), 0, nullptr, nullptr, st))) return rc;
     const ndq_spinor* target = b2 ? b2 : &B[1];
     {
         const ndq_spinor* v[3] = {src, b1, b2};
         const Coef c[3] = {host(ap.a[0]), host(0.5 * zb), host(-1.0)};
-        if ((rc = q_combo(g, U, m, &T, target, host(0.5 * za), b2 ? 3 : 2, v, c, nullptr, st))) return rc;
+        if ((rc = q_any(g, U, m, &T, target, host(0.5 * za), b2 ? 3 : 2, v, c, st))) return rc;
     }
-    *qcount += 2;
+    *qcount += 2 * nr;
     // out = Q (P src) / lam
-    *qcount += 1;
-    return q_combo(g, U, m, target, out, host(1.0 / lam), 0, nullptr, nullptr, nullptr, st);
+    *qcount += nr;
+    return q_any(g, U, m, target, out, host(1.0 / lam), 0, nullptr, nullptr, st);
 }
 
 // out = X sum_l beta_l (X^2 + sigma_l)^{-1} src by multi-shift CG.
@@ -289,7 +300,8 @@ int check_params(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params
     if (!rc) rc = check_spinor(g, out, NDQ_FULL, "sign out");
     if (!rc) rc = check_pair(U, in);
     if (rc) return rc;
-    if (in->nrhs != 1 || out->nrhs != 1) return fail(NDQ_EINVAL, "sign: one right-hand side per call");
+    if (in->nrhs != out->nrhs) return fail(NDQ_EINVAL, "sign: in and out must hold the same number of fields");
+    if (in->nrhs > NDQ_MAX_BATCH) return fail(NDQ_EINVAL, "sign: at most %d right-hand sides per call", NDQ_MAX_BATCH);
     if (in->prec != out->prec) return fail(NDQ_EINVAL, "sign: in and out must share precision");
     if (in->data == out->data) return fail(NDQ_EINVAL, "sign: in and out must not alias");
     if (!p->approx) return fail(NDQ_EINVAL, "sign: no approximant");
@@ -307,28 +319,108 @@ int check_params(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params
 
 }  // namespace
 
-size_t sign_workspace(const ndq_geom* g, const ndq_overlap_params* p, int prec) {
-    Arena ar{nullptr, 0};
-    take_scratch(ar, g, p->nev);
-    if (p->nev > 0 && p->form == NDQ_SANDWICH) ws_spinor(ar, g, prec);
+size_t sign_workspace(const ndq_geom* g, const ndq_overlap_params* p, int prec, int nr) {
     const Approx* ap = reinterpret_cast<const Approx*>(p->approx);
+    // the rational approximant runs one field at a time
+    const int nb = ap->kind == NDQ_MINMAX_POLY ? nr : 1;
+    Arena ar{nullptr, 0};
+    take_scratch(ar, g, p->nev, nb);
+    if (p->nev > 0 && p->form == NDQ_SANDWICH) ws_block(ar, g, prec, nb);
+    if (p->nev > 0 && nb > 1 && prec == NDQ_F16) ws_block(ar, g, NDQ_F32, nb);
     const size_t vb = (size_t)spinor_rhs_bytes(g, prec, NDQ_FULL);
-    if (ap->kind == NDQ_MINMAX_POLY) {
-        for (int i = 0; i < 3; ++i) ws_spinor(ar, g, prec);
-    } else {
-        for (int i = 0; i < 3; ++i) ws_spinor(ar, g, prec);
-        ar.take(vb * ap->n);
-    }
+    for (int i = 0; i < 3; ++i) ws_block(ar, g, prec, nb);
+    if (ap->kind != NDQ_MINMAX_POLY) ar.take(vb * ap->n);
     return ar.used + 256;
 }
+
+namespace {
+
+// Eq. 11 for a block of fields: out_r = in_r + sum_k coef[k][r] u_k with the
+// coefficients in sc.coef; F16 fields pass through the F32 block t32.
+int project_block(const ndq_geom* g, const ndq_overlap_params* p, const Scratch& sc, const ndq_spinor* in,
+                  const ndq_spinor* out, const ndq_spinor* t32, hipStream_t st) {
+    if (out->prec != NDQ_F16) return mode_update_block(g, p->modes, p->nev, sc.coef, in, out, st);
+    int rc = mode_update_block(g, p->modes, p->nev, sc.coef, in, t32, st);
+    if (!rc) rc = convert(g, out, t32, st);
+    return rc;
+}
+
+// sign(Q) on a block of fields with the polynomial approximant: every stencil
+// application of the recurrence serves the whole block (links loaded once per
+// tile), and the projections of Eq. 11 run as block products with the modes.
+int apply_sign_block(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p, const ndq_spinor* in,
+                     const ndq_spinor* out, Arena& ar, ndq_stats* stats, hipStream_t st) {
+    const Approx& ap = *reinterpret_cast<const Approx*>(p->approx);
+    const int nev = p->nev;
+    const int nr = in->nrhs;
+    Scratch sc = take_scratch(ar, g, nev, nr);
+    ndq_spinor t32;
+    memset(&t32, 0, sizeof(t32));
+    if (nev > 0 && in->prec == NDQ_F16) t32 = ws_block(ar, g, NDQ_F32, nr);
+    if (ar.overflow) return fail(NDQ_ENOMEM, "sign: workspace too small");
+    ModeSigns sg;
+    for (int k = 0; k < NDQ_MAX_MODES; ++k) sg.s[k] = k < nev ? (p->nu[k] > 0 ? 1.0f : -1.0f) : 0.0f;
+    const ndq_spinor* src = in;
+    ndq_spinor defl;
+    int rc;
+    if (nev > 0) {
+        // c[k][r] = <u_k, in_r>
+        if ((rc = gram_block(g, p->modes, nev, in, sc.partials, sc.dots_c, st))) return rc;
+        if (p->form == NDQ_SANDWICH) {
+            defl = ws_block(ar, g, in->prec, nr);
+            if (ar.overflow) return fail(NDQ_ENOMEM, "sign: workspace too small");
+            if ((rc = mode_coef_block(sc.dots_c, nullptr, sg, 0, nev, nr, -1.0, 0.0, sc.coef, st))) return rc;
+            if ((rc = project_block(g, p, sc, in, &defl, &t32, st))) return rc;
+            src = &defl;
+        }
+    }
+    int64_t q = 0;
+    rc = poly_apply(g, U, p->m, ap, p->lam_max, src, out, ar, &q, st);
+    if (stats) {
+        stats->q_applies += q;
+        stats->iterations += ap.n;
+        stats->residual = 0.0;
+    }
+    if (rc) return rc;
+    if (nev > 0) {
+        // out_r <- t_r + sum_k (sign(nu_k) c[k][r] - <u_k, t_r>) u_k   (Eq. 11)
+        if ((rc = gram_block(g, p->modes, nev, out, sc.partials, sc.dots_d, st))) return rc;
+        if ((rc = mode_coef_block(sc.dots_c, sc.dots_d, sg, 1, nev, nr, 1.0, -1.0, sc.coef, st))) return rc;
+        if ((rc = project_block(g, p, sc, out, out, &t32, st))) return rc;
+    }
+    return NDQ_OK;
+}
+
+}  // namespace
 
 int apply_sign(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p, const ndq_spinor* in,
                const ndq_spinor* out, Arena& ar, ndq_stats* stats, hipStream_t st) {
     int rc = check_params(g, U, p, in, out);
     if (rc) return rc;
     const Approx& ap = *reinterpret_cast<const Approx*>(p->approx);
+    if (in->nrhs > 1) {
+        if (ap.kind == NDQ_MINMAX_POLY) return apply_sign_block(g, U, p, in, out, ar, stats, st);
+        // the rational approximant: one field at a time (multi-shift CG keeps
+        // scalars per field); every field reuses the same workspace
+        const size_t mark = ar.used;
+        for (int r = 0; r < in->nrhs; ++r) {
+            ar.used = mark;
+            ar.overflow = false;
+            const ndq_spinor i1 = rhs_slice(g, in, r), o1 = rhs_slice(g, out, r);
+            ndq_stats s1;
+            memset(&s1, 0, sizeof(s1));
+            if ((rc = apply_sign(g, U, p, &i1, &o1, ar, &s1, st))) return rc;
+            if (stats) {
+                stats->q_applies += s1.q_applies;
+                stats->iterations += s1.iterations;
+                stats->residual = std::max(stats->residual, s1.residual);
+            }
+        }
+        return NDQ_OK;
+    }
     const int nev = p->nev;
     Scratch sc = take_scratch(ar, g, nev);
+
     if (ar.overflow) return fail(NDQ_ENOMEM, "sign: workspace too small");
     ModeSigns sg;
     for (int k = 0; k < NDQ_MAX_MODES; ++k) sg.s[k] = k < nev ? (p->nu[k] > 0 ? 1.0f : -1.0f) : 0.0f;
@@ -374,11 +466,17 @@ using namespace ndq;
 
 extern "C" {
 
-size_t ndq_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p, int prec, int op) {
-    if (!g || !p || !p->approx || prec < NDQ_F64 || prec > NDQ_F16 || p->nev < 0 || p->nev > NDQ_MAX_MODES) return 0;
-    size_t b = sign_workspace(g, p, prec);
-    if (op == NDQ_OP_DN) b += (size_t)spinor_rhs_bytes(g, prec, NDQ_FULL) + 256;
+size_t ndq_workspace_bytes_nrhs(const ndq_geom* g, const ndq_overlap_params* p, int prec, int op, int nrhs) {
+    if (!g || !p || !p->approx || prec < NDQ_F64 || prec > NDQ_F16 || p->nev < 0 || p->nev > NDQ_MAX_MODES ||
+        nrhs < 1 || nrhs > NDQ_MAX_BATCH)
+        return 0;
+    size_t b = sign_workspace(g, p, prec, nrhs);
+    if (op == NDQ_OP_DN) b += (size_t)spinor_rhs_bytes(g, prec, NDQ_FULL) * nrhs + 256;
     return b;
+}
+
+size_t ndq_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p, int prec, int op) {
+    return ndq_workspace_bytes_nrhs(g, p, prec, op, 1);
 }
 
 int ndq_apply_sign(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params* p, const ndq_spinor* in,
@@ -399,7 +497,7 @@ int ndq_apply_DN(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params
     if (rc) return rc;
     hipStream_t st = as_stream(stream);
     Arena ar{static_cast<char*>(ws), ws_bytes};
-    ndq_spinor S = ws_spinor(ar, g, in->prec);
+    ndq_spinor S = ws_block(ar, g, in->prec, in->nrhs);
     if (ar.overflow) return fail(NDQ_ENOMEM, "D_N: workspace too small");
     if ((rc = apply_sign(g, U, p, in, &S, ar, stats, st))) return rc;
     // D_N^m in = (1/abar - mq/2)(in + gamma5 S in) + mq in, 1/abar = 1 + s = -m

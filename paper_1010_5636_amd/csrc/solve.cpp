@@ -25,6 +25,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 
 #include "ndq_solver.h"
@@ -271,6 +272,100 @@ int dh_apply(DOp& d, const ndq_spinor* y, const ndq_spinor* tmp, const ndq_spino
     return lincomb(d.g, d.prec, out, 2, src, cf, nullptr, nullptr, d.st);
 }
 
+// |x_r|^2 of every field of a block, to the host (nr values).
+int host_norms(const ndq_geom* g, const ndq_spinor* x, double* partials, double* dscal, double* out, hipStream_t st) {
+    int rc = dot(g, x, nullptr, partials, dscal, st);
+    if (rc) return rc;
+    NDQ_HIP(hipMemcpyAsync(out, dscal, sizeof(double) * x->nrhs, hipMemcpyDeviceToHost, st));
+    NDQ_HIP(hipStreamSynchronize(st));
+    for (int r = 0; r < x->nrhs; ++r)
+        if (!isfinite(out[r])) return fail(NDQ_ENAN, "solve: NaN or Inf in the norm of right-hand side %d", r);
+    return NDQ_OK;
+}
+
+// CGNE for D e_r = rhs_r on every field r of a block at once: one D (or D^H)
+// application of the whole block per step, so that each sign application is
+// shared (links loaded once per stencil tile for all fields), and scalars per
+// field.  A field stops (its coefficients become those of the identity) once
+// its residual is below tol |rhs_r|, or from the start if active[r] is 0;
+// e starts at zero.  Returns the number of block iterations.
+int cgne_block(DOp& d, const ndq_spinor* rhs, Vecs& v, double tol, int max_iter, const int* active, double* partials,
+               double* dscal, int* iters) {
+    const ndq_geom* g = d.g;
+    hipStream_t st = d.st;
+    const int nr = rhs->nrhs;
+    int rc;
+    double r0[NDQ_MAX_BATCH], ss[NDQ_MAX_BATCH], zz[NDQ_MAX_BATCH], qq[NDQ_MAX_BATCH], zn[NDQ_MAX_BATCH];
+    double cf[2 * NDQ_MAX_BATCH];
+    int act[NDQ_MAX_BATCH];
+    if ((rc = lincomb(g, d.prec, &v.e, 0, nullptr, nullptr, nullptr, nullptr, st))) return rc;
+    {
+        const ndq_spinor* src[1] = {rhs};
+        const Coef c1[1] = {hc(1.0)};
+        if ((rc = lincomb(g, d.prec, &v.s, 1, src, c1, nullptr, nullptr, st))) return rc;
+    }
+    if ((rc = host_norms(g, &v.s, partials, dscal, r0, st))) return rc;
+    int nact = 0;
+    for (int r = 0; r < nr; ++r) {
+        act[r] = active[r] && r0[r] > 0.0;
+        nact += act[r];
+    }
+    *iters = 0;
+    if (!nact) return NDQ_OK;
+    // z = D^H s, p = z
+    if ((rc = dh_apply(d, &v.s, &v.t, &v.z))) return rc;
+    {
+        const ndq_spinor* src[1] = {&v.z};
+        const Coef c1[1] = {hc(1.0)};
+        if ((rc = lincomb(g, d.prec, &v.p, 1, src, c1, nullptr, nullptr, st))) return rc;
+    }
+    if ((rc = host_norms(g, &v.z, partials, dscal, zz, st))) return rc;
+    int it = 0;
+    while (it < max_iter && nact > 0) {
+        if ((rc = d_apply(d, &v.p, &v.q))) return rc;
+        if ((rc = host_norms(g, &v.q, partials, dscal, qq, st))) return rc;
+        // e += alpha p, s -= alpha q
+        for (int r = 0; r < nr; ++r) {
+            if (act[r] && !(qq[r] > 0.0)) act[r] = 0;
+            const double alpha = act[r] ? zz[r] / qq[r] : 0.0;
+            cf[r] = 1.0;
+            cf[nr + r] = alpha;
+        }
+        {
+            const ndq_spinor* src[2] = {&v.e, &v.p};
+            if ((rc = lincomb_rhs(g, d.prec, &v.e, 2, src, cf, nullptr, nullptr, st))) return rc;
+            for (int r = 0; r < nr; ++r) cf[nr + r] = -cf[nr + r];
+            const ndq_spinor* src2[2] = {&v.s, &v.q};
+            if ((rc = lincomb_rhs(g, d.prec, &v.s, 2, src2, cf, nullptr, nullptr, st))) return rc;
+        }
+        if ((rc = host_norms(g, &v.s, partials, dscal, ss, st))) return rc;
+        ++it;
+        nact = 0;
+        for (int r = 0; r < nr; ++r) {
+            if (act[r] && ss[r] <= tol * tol * r0[r]) act[r] = 0;
+            nact += act[r];
+        }
+        if (!nact) break;
+        // z = D^H s, p = z + beta p (stopped fields keep p)
+        if ((rc = dh_apply(d, &v.s, &v.t, &v.z))) return rc;
+        if ((rc = host_norms(g, &v.z, partials, dscal, zn, st))) return rc;
+        for (int r = 0; r < nr; ++r) {
+            if (act[r]) {
+                cf[r] = 1.0;
+                cf[nr + r] = zn[r] / zz[r];
+                zz[r] = zn[r];
+            } else {
+                cf[r] = 0.0;
+                cf[nr + r] = 1.0;
+            }
+        }
+        const ndq_spinor* src[2] = {&v.z, &v.p};
+        if ((rc = lincomb_rhs(g, d.prec, &v.p, 2, src, cf, nullptr, nullptr, st))) return rc;
+    }
+    *iters = it;
+    return NDQ_OK;
+}
+
 int check_solve(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, const ndq_overlap_params* p64,
                 const ndq_overlap_params* plo, const ndq_solve_params* sp, const ndq_spinor* b, const ndq_spinor* x) {
     if (!g || !p64 || !sp) return fail(NDQ_EINVAL, "solve: NULL argument");
@@ -280,7 +375,8 @@ int check_solve(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, c
     if (rc) return rc;
     if (U64->prec != NDQ_F64 || b->prec != NDQ_F64 || x->prec != NDQ_F64)
         return fail(NDQ_EPREC, "solve: b, x and the outer links are F64");
-    if (b->nrhs != 1 || x->nrhs != 1) return fail(NDQ_EINVAL, "solve: one right-hand side per call");
+    if (b->nrhs != x->nrhs) return fail(NDQ_EINVAL, "solve: b and x must hold the same number of fields");
+    if (b->nrhs > NDQ_MAX_BATCH) return fail(NDQ_EINVAL, "solve: at most %d right-hand sides per call", NDQ_MAX_BATCH);
     if (sp->inner_prec != NDQ_F64) {
         if (!Ulo || !plo) return fail(NDQ_EINVAL, "solve: mixed precision needs inner links and parameters");
         if ((rc = check_gauge(Ulo))) return rc;
@@ -291,41 +387,16 @@ int check_solve(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, c
     return NDQ_OK;
 }
 
-}  // namespace
-}  // namespace ndq
 
-using namespace ndq;
 
-extern "C" {
-
-size_t ndq_solve_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p64_in, const ndq_overlap_params* plo_in,
-                                 const ndq_solve_params* sp) {
-    if (!g || !p64_in || !p64_in->approx || !sp) return 0;
-    const ndq_overlap_params h64 = hermitian_form(p64_in);
-    const ndq_overlap_params hlo = plo_in ? hermitian_form(plo_in) : h64;
-    const ndq_overlap_params* p64 = &h64;
-    const ndq_overlap_params* plo = plo_in ? &hlo : nullptr;
-    const int lo = sp->inner_prec;
-    const ndq_overlap_params* pi = lo == NDQ_F64 ? p64 : plo;
-    if (!pi || !pi->approx) return 0;
-    size_t b = 0;
-    b += 3 * ((size_t)spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL) + 256);        // r, t64, S64
-    b += 8 * ((size_t)spinor_rhs_bytes(g, lo, NDQ_FULL) + 256);             // r_lo, S_lo, e s z p q t
-    b += partials_capacity(g, 2) + 1024;
-    const size_t s64 = sign_workspace(g, p64, NDQ_F64);
-    const size_t slo = sign_workspace(g, pi, lo);
-    return b + std::max(s64, slo) + 4096;
-}
-
-int ndq_solve_DN(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, const ndq_overlap_params* p64_in,
+int solve_single(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, const ndq_overlap_params* p64_in,
                  const ndq_overlap_params* plo_in, const ndq_solve_params* sp, const ndq_spinor* b, const ndq_spinor* x,
                  void* ws, size_t ws_bytes, ndq_stats* stats, void* stream) {
     const auto t0 = std::chrono::steady_clock::now();
     ndq_stats local;
     ndq_stats* stt = stats ? stats : &local;
     memset(stt, 0, sizeof(*stt));
-    int rc = check_solve(g, U64, Ulo, p64_in, plo_in, sp, b, x);
-    if (rc) return rc;
+    int rc;
     // CGNE takes D^H = gamma5 D gamma5, which needs a Hermitian sign(Q): the
     // operators of the solve use the sandwich form of Eq. 11
     const ndq_overlap_params h64 = hermitian_form(p64_in);
@@ -413,6 +484,164 @@ int ndq_solve_DN(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, 
     stt->iterations = (int32_t)stt->inner;
     stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return NDQ_OK;
+}
+
+
+// Block solve: FP64 defect correction with one CGNE per field in the inner
+// precision, all fields of the block sharing every D application.  The
+// residual reported is the largest over the fields; `inner` counts block
+// iterations.
+int solve_block(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, const ndq_overlap_params* p64_in,
+                const ndq_overlap_params* plo_in, const ndq_solve_params* sp, const ndq_spinor* b, const ndq_spinor* x,
+                void* ws, size_t ws_bytes, ndq_stats* stt, hipStream_t st) {
+    const ndq_overlap_params h64 = hermitian_form(p64_in);
+    const ndq_overlap_params hlo = plo_in ? hermitian_form(plo_in) : h64;
+    const ndq_overlap_params* p64 = &h64;
+    const ndq_overlap_params* plo = plo_in ? &hlo : nullptr;
+    const int lo = sp->inner_prec;
+    const int nr = b->nrhs;
+    const ndq_gauge* Ui = lo == NDQ_F64 ? U64 : Ulo;
+    const ndq_overlap_params* pi = lo == NDQ_F64 ? p64 : plo;
+    Arena ar{static_cast<char*>(ws), ws_bytes};
+    ndq_spinor r = ws_block(ar, g, NDQ_F64, nr), t64 = ws_block(ar, g, NDQ_F64, nr), S64 = ws_block(ar, g, NDQ_F64, nr);
+    ndq_spinor rlo = ws_block(ar, g, lo, nr), Slo = ws_block(ar, g, lo, nr);
+    Vecs v{ws_block(ar, g, lo, nr), ws_block(ar, g, lo, nr), ws_block(ar, g, lo, nr), ws_block(ar, g, lo, nr),
+           ws_block(ar, g, lo, nr), ws_block(ar, g, lo, nr)};
+    double* partials = static_cast<double*>(ar.take(partials_capacity(g, 2 * nr)));
+    double* dscal = static_cast<double*>(ar.take((64 + 2 * nr) * sizeof(double)));
+    if (ar.overflow) return fail(NDQ_ENOMEM, "solve: workspace too small (need %zu bytes)", ar.used);
+    const size_t mark = ar.used;
+    DOp d64{g, U64, p64, NDQ_F64, st, &ar, mark, stt, S64};
+    DOp dlo{g, Ui, pi, lo, st, &ar, mark, stt, Slo};
+    int rc;
+    double bb[NDQ_MAX_BATCH], rr[NDQ_MAX_BATCH], rn[NDQ_MAX_BATCH], cf[2 * NDQ_MAX_BATCH];
+    int act[NDQ_MAX_BATCH];
+    if ((rc = host_norms(g, b, partials, dscal, bb, st))) return rc;
+    // a zero right-hand side has the solution zero
+    bool any_zero = false;
+    for (int j = 0; j < nr; ++j) {
+        cf[j] = bb[j] == 0.0 ? 0.0 : 1.0;
+        any_zero |= bb[j] == 0.0;
+    }
+    if (any_zero) {
+        const ndq_spinor* s1[1] = {x};
+        if ((rc = lincomb_rhs(g, NDQ_F64, x, 1, s1, cf, nullptr, nullptr, st))) return rc;
+    }
+    const int max_outer = sp->max_outer > 0 ? sp->max_outer : 20;
+    const int max_inner = sp->max_inner > 0 ? sp->max_inner : 100000;
+    const double inner_tol = sp->inner_tol > 0 ? sp->inner_tol : (lo == NDQ_F64 ? 0.5 * sp->tol : 1e-5);
+    for (int outer = 0;; ++outer) {
+        // r = b - D x (FP64)
+        if ((rc = d_apply(d64, x, &t64))) return rc;
+        const ndq_spinor* src[2] = {b, &t64};
+        const Coef c2[2] = {Coef{1.0, nullptr}, Coef{-1.0, nullptr}};
+        if ((rc = lincomb(g, NDQ_F64, &r, 2, src, c2, nullptr, nullptr, st))) return rc;
+        if ((rc = host_norms(g, &r, partials, dscal, rr, st))) return rc;
+        int nact = 0;
+        double worst = 0.0;
+        for (int j = 0; j < nr; ++j) {
+            const double res = bb[j] > 0.0 ? sqrt(rr[j] / bb[j]) : 0.0;
+            worst = std::max(worst, res);
+            act[j] = res > sp->tol;
+            nact += act[j];
+            rn[j] = sqrt(rr[j]);
+        }
+        stt->residual = worst;
+        stt->outer = outer;
+        if (!nact) break;
+        if (outer >= max_outer)
+            return fail(NDQ_ENOCONV, "solve: largest residual %.3e after %d outer steps", worst, outer);
+        // r_lo = r / |r| on the fields still above the target, zero elsewhere
+        for (int j = 0; j < nr; ++j) cf[j] = act[j] ? 1.0 / rn[j] : 0.0;
+        const ndq_spinor* s1[1] = {&r};
+        if (lo == NDQ_F64) {
+            if ((rc = lincomb_rhs(g, NDQ_F64, &rlo, 1, s1, cf, nullptr, nullptr, st))) return rc;
+        } else {
+            if ((rc = lincomb_rhs(g, NDQ_F64, &t64, 1, s1, cf, nullptr, nullptr, st))) return rc;
+            if ((rc = convert(g, &rlo, &t64, st))) return rc;
+        }
+        int its = 0;
+        if ((rc = cgne_block(dlo, &rlo, v, inner_tol, max_inner, act, partials, dscal, &its))) return rc;
+        stt->inner += its;
+        const ndq_spinor* ex = &v.e;
+        if (lo != NDQ_F64) {
+            if ((rc = convert(g, &t64, &v.e, st))) return rc;
+            ex = &t64;
+        }
+        // x += |r| e
+        for (int j = 0; j < nr; ++j) {
+            cf[j] = 1.0;
+            cf[nr + j] = act[j] ? rn[j] : 0.0;
+        }
+        const ndq_spinor* s2[2] = {x, ex};
+        if ((rc = lincomb_rhs(g, NDQ_F64, x, 2, s2, cf, nullptr, nullptr, st))) return rc;
+    }
+    return NDQ_OK;
+}
+
+}  // namespace
+}  // namespace ndq
+
+using namespace ndq;
+
+extern "C" {
+
+size_t ndq_solve_workspace_bytes_nrhs(const ndq_geom* g, const ndq_overlap_params* p64_in,
+                                      const ndq_overlap_params* plo_in, const ndq_solve_params* sp, int nrhs) {
+    if (!g || !p64_in || !p64_in->approx || !sp || nrhs < 1 || nrhs > NDQ_MAX_BATCH) return 0;
+    const ndq_overlap_params h64 = hermitian_form(p64_in);
+    const ndq_overlap_params hlo = plo_in ? hermitian_form(plo_in) : h64;
+    const ndq_overlap_params* p64 = &h64;
+    const ndq_overlap_params* plo = plo_in ? &hlo : nullptr;
+    const int lo = sp->inner_prec;
+    const ndq_overlap_params* pi = lo == NDQ_F64 ? p64 : plo;
+    if (!pi || !pi->approx) return 0;
+    // the chirality-sector solver runs the fields one after the other
+    const int nr = sp->sectors ? 1 : nrhs;
+    size_t b = 0;
+    b += 3 * ((size_t)spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL) * nr + 256);   // r, t64, S64
+    b += 8 * ((size_t)spinor_rhs_bytes(g, lo, NDQ_FULL) * nr + 256);        // r_lo, S_lo, e s z p q t
+    b += partials_capacity(g, 2 * nr) + (64 + 2 * nr) * sizeof(double) + 1024;
+    const size_t s64 = sign_workspace(g, p64, NDQ_F64, nr);
+    const size_t slo = sign_workspace(g, pi, lo, nr);
+    return b + std::max(s64, slo) + 4096;
+}
+
+size_t ndq_solve_workspace_bytes(const ndq_geom* g, const ndq_overlap_params* p64_in, const ndq_overlap_params* plo_in,
+                                 const ndq_solve_params* sp) {
+    return ndq_solve_workspace_bytes_nrhs(g, p64_in, plo_in, sp, 1);
+}
+
+int ndq_solve_DN(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, const ndq_overlap_params* p64_in,
+                 const ndq_overlap_params* plo_in, const ndq_solve_params* sp, const ndq_spinor* b, const ndq_spinor* x,
+                 void* ws, size_t ws_bytes, ndq_stats* stats, void* stream) {
+    const auto t0 = std::chrono::steady_clock::now();
+    ndq_stats local;
+    ndq_stats* stt = stats ? stats : &local;
+    memset(stt, 0, sizeof(*stt));
+    int rc = check_solve(g, U64, Ulo, p64_in, plo_in, sp, b, x);
+    if (rc) return rc;
+    if (b->nrhs == 1) return solve_single(g, U64, Ulo, p64_in, plo_in, sp, b, x, ws, ws_bytes, stt, stream);
+    if (sp->sectors) {
+        // one field after the other, each with the whole workspace
+        for (int r = 0; r < b->nrhs; ++r) {
+            const ndq_spinor b1 = rhs_slice(g, b, r), x1 = rhs_slice(g, x, r);
+            ndq_stats s1;
+            rc = solve_single(g, U64, Ulo, p64_in, plo_in, sp, &b1, &x1, ws, ws_bytes, &s1, stream);
+            stt->q_applies += s1.q_applies;
+            stt->inner += s1.inner;
+            stt->outer = std::max(stt->outer, s1.outer);
+            stt->residual = std::max(stt->residual, s1.residual);
+            if (rc) break;
+        }
+        stt->iterations = (int32_t)stt->inner;
+        stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return rc;
+    }
+    rc = solve_block(g, U64, Ulo, p64_in, plo_in, sp, b, x, ws, ws_bytes, stt, as_stream(stream));
+    stt->iterations = (int32_t)stt->inner;
+    stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
 }
 
 }  // extern "C"

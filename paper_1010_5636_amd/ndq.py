@@ -150,6 +150,7 @@ _SIG = {
     "ndq_approx_coeffs": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "ndq_approx_destroy": (None, [_P]),
     "ndq_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(_Params), _I, _I]),
+    "ndq_workspace_bytes_nrhs": (ctypes.c_size_t, [_P, ctypes.POINTER(_Params), _I, _I, _I]),
     "ndq_apply_sign": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Params), ctypes.POINTER(_Spinor),
                             ctypes.POINTER(_Spinor), _P, ctypes.c_size_t, ctypes.POINTER(_Stats), _P]),
     "ndq_apply_DN": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Params), ctypes.POINTER(_Spinor),
@@ -167,6 +168,8 @@ _SIG = {
                           ctypes.POINTER(_Spinor), ctypes.POINTER(_IndexInfo), _P, ctypes.c_size_t, _P]),
     "ndq_solve_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(_Params), ctypes.POINTER(_Params),
                                                     ctypes.POINTER(_SolveParams)]),
+    "ndq_solve_workspace_bytes_nrhs": (ctypes.c_size_t, [_P, ctypes.POINTER(_Params), ctypes.POINTER(_Params),
+                                                         ctypes.POINTER(_SolveParams), _I]),
     "ndq_solve_DN": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Gauge), ctypes.POINTER(_Params),
                           ctypes.POINTER(_Params), ctypes.POINTER(_SolveParams), ctypes.POINTER(_Spinor),
                           ctypes.POINTER(_Spinor), _P, ctypes.c_size_t, ctypes.POINTER(_Stats), _P]),
@@ -441,10 +444,10 @@ class Overlap:
                          int(max_iter), int(check_every), int(bool(graph)))
         self._ws = {}
 
-    def workspace(self, prec: int, op: int):
-        key = (prec, op)
+    def workspace(self, prec: int, op: int, nrhs: int = 1):
+        key = (prec, op, nrhs)
         if key not in self._ws:
-            n = int(lib().ndq_workspace_bytes(self.geom.handle, ctypes.byref(self.p), prec, op))
+            n = int(lib().ndq_workspace_bytes_nrhs(self.geom.handle, ctypes.byref(self.p), prec, op, nrhs))
             if n == 0:
                 raise NdqError(-1, "invalid parameters for ndq_workspace_bytes")
             self._ws[key] = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -452,7 +455,7 @@ class Overlap:
 
 
 def apply_sign(geom: Geometry, U: GaugeField, ov: Overlap, inp: SpinorField, out: SpinorField, stream=None) -> dict:
-    ws = ov.workspace(inp.prec, OP_SIGN)
+    ws = ov.workspace(inp.prec, OP_SIGN, inp.nrhs)
     st = _Stats()
     _check(lib().ndq_apply_sign(geom.handle, ctypes.byref(U.desc), ctypes.byref(ov.p), ctypes.byref(inp.desc),
                                 ctypes.byref(out.desc), _ptr(ws), ws.numel(), ctypes.byref(st), _stream(stream)))
@@ -460,7 +463,7 @@ def apply_sign(geom: Geometry, U: GaugeField, ov: Overlap, inp: SpinorField, out
 
 
 def apply_DN(geom: Geometry, U: GaugeField, ov: Overlap, inp: SpinorField, out: SpinorField, stream=None) -> dict:
-    ws = ov.workspace(inp.prec, OP_DN)
+    ws = ov.workspace(inp.prec, OP_DN, inp.nrhs)
     st = _Stats()
     _check(lib().ndq_apply_DN(geom.handle, ctypes.byref(U.desc), ctypes.byref(ov.p), ctypes.byref(inp.desc),
                               ctypes.byref(out.desc), _ptr(ws), ws.numel(), ctypes.byref(st), _stream(stream)))
@@ -540,12 +543,13 @@ def solve_DN(geom: Geometry, U64: GaugeField, ov64: Overlap, b: SpinorField, x: 
              U_lo: GaugeField | None = None, ov_lo: Overlap | None = None, inner_prec: int = F64,
              inner_tol: float = 0.0, max_outer: int = 20, max_inner: int = 0, sectors: bool = False,
              stream=None) -> dict:
-    """x = (D_N^m)^{-1} b; x holds the initial guess (e.g. zeros) on entry.  ``sectors``:
-    CG on the chirality sectors of D^H D instead of CGNE."""
+    """x = (D_N^m)^{-1} b for every right-hand side of b (up to 32, all sharing
+    each application of D); x holds the initial guess (e.g. zeros) on entry.
+    ``sectors``: CG on the chirality sectors of D^H D instead of CGNE."""
     sp = _SolveParams(float(tol), int(max_outer), int(max_inner), float(inner_tol), int(inner_prec),
                       int(bool(sectors)))
     plo = ctypes.byref(ov_lo.p) if ov_lo is not None else None
-    n = int(lib().ndq_solve_workspace_bytes(geom.handle, ctypes.byref(ov64.p), plo, ctypes.byref(sp)))
+    n = int(lib().ndq_solve_workspace_bytes_nrhs(geom.handle, ctypes.byref(ov64.p), plo, ctypes.byref(sp), b.nrhs))
     if n == 0:
         raise NdqError(-1, "bad solve parameters")
     ws = torch.empty(n, dtype=torch.uint8, device="cuda")
