@@ -270,7 +270,9 @@ typedef struct {
     double tol;           /* target true residual |b - D x| / |b|, D the FP64 operator of p64 */
     int32_t max_outer;    /* defect-correction steps (<= 0: 20)                             */
     int32_t max_inner;    /* CG iterations per inner solve (<= 0: no limit)                 */
-    double inner_tol;     /* inner relative residual (<= 0: 1e-5 mixed, tol/2 plain FP64)   */
+    double inner_tol;     /* inner relative residual (<= 0: tol/2 plain FP64, 1e-5 for F32
+                             storage, 8 * 2^-11 = 3.9e-3 for F16 storage: eight units of its
+                             rounding)                                                        */
     int32_t inner_prec;   /* NDQ_F64: plain FP64 solve; NDQ_F32 / NDQ_F16: mixed precision  */
     int32_t sectors;      /* inner solver: 0 = CGNE on D^H D (two sign applies per iteration);
                              1 = CG on each chirality sector of D^H D, which commutes with
@@ -453,6 +455,24 @@ int ndq_set_launch(int block, int xcd_remap);
 /* The same for one storage format only (spinor precision, link precision,
  * recon); the autotuner records its choice per format this way. */
 int ndq_set_launch_for(int sprec, int lprec, int recon, int block, int xcd_remap);
+
+/* Work order of the multi-right-hand-side stencil (nrhs > 1: ndq_apply_Q,
+ * ndq_apply_dslash and the block forms of sign, D_N and solve) for one lattice
+ * g, storage format (spinor precision, link precision, recon), nrhs and number
+ * ny of output parities per launch (1: dslash, 2: Q): rg right-hand sides per
+ * workgroup of 64 sites (0: all nrhs; the links of a tile are staged in LDS
+ * once per workgroup), group_major = 1 runs every tile for one group of rg
+ * fields before the next group (the neighbour spinors re-read by nearby tiles
+ * then stay in the caches), 0 runs the groups of a tile next to each other;
+ * chunk: -1 automatic, 0 tiles in index order, c > 0 c consecutive tiles of
+ * every time slice in turn (c must divide the 64-site tiles of a slice);
+ * xcd_remap as in ndq_set_launch; link_nt: links loaded with the non-temporal
+ * hint (1), without (0), or automatic (-1: when each link is read once).
+ * Results do not depend on the work order.  Process-wide.  Errors: NDQ_EINVAL. */
+int ndq_set_mrhs_launch(const ndq_geom* g, int sprec, int lprec, int recon, int nrhs, int ny, int rg,
+                        int group_major, int chunk, int xcd_remap, int link_nt);
+int ndq_get_mrhs_launch(const ndq_geom* g, int sprec, int lprec, int recon, int nrhs, int ny, int* rg,
+                        int* group_major, int* chunk, int* xcd_remap, int* link_nt);
 
 /* The launch shape currently used for one storage format (host outputs). */
 int ndq_get_launch_for(int sprec, int lprec, int recon, int* block, int* xcd_remap);

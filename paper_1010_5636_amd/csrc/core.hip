@@ -177,12 +177,97 @@ size_t ndq_spinor_bytes(const ndq_geom* g, int prec, int parity, int nrhs) {
 
 #include "wilson.h"
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace ndq {
 namespace {
 Tuning g_tuning[3][3][3];
+
+using MrhsKey = std::tuple<int, int, int, int, int, int, int, int, int, int>;
+std::mutex g_mrhs_mu;
+std::map<MrhsKey, MrhsShape> g_mrhs;
+
+MrhsKey mrhs_key(const GeomK& g, int sprec, int lprec, int recon, int nrhs, int ny) {
+    return MrhsKey{g.n0, g.n1, g.n2, g.n3, sprec, lprec, recon, nrhs, ny, 0};
 }
+}  // namespace
+
 Tuning& tuning(int sprec, int lprec, int recon) { return g_tuning[sprec][lprec][recon_index(recon)]; }
+
+// Defaults from a sweep of the work order on 24^3x48 and 32^3x64 (12 and 60
+// fields): blocks of 8 or more F32/F64 fields run in group-major order with 6
+// fields per workgroup, and the tiles in chunks spanning two x1 rows of the
+// slice (the smallest divisor c of the slice's tiles with 64 c >= 2 s1), so
+// that the neighbour spinors of nearby tiles are still in L2 when re-read.
+// F16 fields (half the bytes per field) keep one group in tile order.
+MrhsShape default_mrhs_shape(const GeomK& g, int sprec, int lprec, int recon, int nrhs, int ny) {
+    (void)lprec; (void)recon; (void)ny;
+    MrhsShape s;
+    if (nrhs >= 8 && sprec != P16) {
+        s.rg = 6;
+        s.group_major = 1;
+        const int64_t per_slice = g.vh / g.n0;
+        if (g.n0 >= 4 && per_slice * g.n0 == g.vh && per_slice % 64 == 0) {
+            const int64_t S = per_slice / 64;
+            for (int64_t c = 1; c <= S; ++c) {
+                if (S % c == 0 && 64 * c >= 2 * (int64_t)g.s1) {
+                    s.chunk = (int)c;
+                    break;
+                }
+            }
+        }
+    }
+    return s;
+}
+
+MrhsShape mrhs_shape(const GeomK& g, int sprec, int lprec, int recon, int nrhs, int ny) {
+    std::lock_guard<std::mutex> lock(g_mrhs_mu);
+    const auto it = g_mrhs.find(mrhs_key(g, sprec, lprec, recon, nrhs, ny));
+    if (it != g_mrhs.end()) return it->second;
+    return default_mrhs_shape(g, sprec, lprec, recon, nrhs, ny);
+}
+
+void set_mrhs_shape(const GeomK& g, int sprec, int lprec, int recon, int nrhs, int ny, const MrhsShape& s) {
+    std::lock_guard<std::mutex> lock(g_mrhs_mu);
+    g_mrhs[mrhs_key(g, sprec, lprec, recon, nrhs, ny)] = s;
+}
 }  // namespace ndq
+
+extern "C" int ndq_set_mrhs_launch(const ndq_geom* g, int sprec, int lprec, int recon, int nrhs, int ny, int rg,
+                                   int group_major, int chunk, int xcd_remap, int link_nt) {
+    if (!g || sprec < NDQ_F64 || sprec > NDQ_F16 || lprec < NDQ_F64 || lprec > NDQ_F16 ||
+        (recon != 18 && recon != 12 && recon != 8) || nrhs < 1 || (ny != 1 && ny != 2) || rg < 0 || chunk < -1)
+        return ndq::fail(NDQ_EINVAL, "ndq_set_mrhs_launch: bad argument");
+    if (chunk > 0) {
+        const int64_t per_slice = g->k.vh / g->k.n0;
+        if (g->k.n0 < 2 || per_slice * g->k.n0 != g->k.vh || per_slice % 64 || (per_slice / 64) % chunk)
+            return ndq::fail(NDQ_EINVAL, "ndq_set_mrhs_launch: chunk %d does not divide the 64-site tiles of a time slice",
+                             chunk);
+    }
+    ndq::MrhsShape s;
+    s.rg = rg;
+    s.group_major = group_major ? 1 : 0;
+    s.chunk = chunk;
+    s.xcd_remap = xcd_remap ? 1 : 0;
+    s.link_nt = link_nt < 0 ? -1 : (link_nt ? 1 : 0);
+    ndq::set_mrhs_shape(g->k, sprec, lprec, recon, nrhs, ny, s);
+    return NDQ_OK;
+}
+
+extern "C" int ndq_get_mrhs_launch(const ndq_geom* g, int sprec, int lprec, int recon, int nrhs, int ny, int* rg,
+                                   int* group_major, int* chunk, int* xcd_remap, int* link_nt) {
+    if (!g || !rg || !group_major || !chunk || !xcd_remap || !link_nt)
+        return ndq::fail(NDQ_EINVAL, "ndq_get_mrhs_launch: NULL argument");
+    const ndq::MrhsShape s = ndq::mrhs_shape(g->k, sprec, lprec, recon, nrhs, ny);
+    *rg = s.rg;
+    *group_major = s.group_major;
+    *chunk = s.chunk;
+    *xcd_remap = s.xcd_remap;
+    *link_nt = s.link_nt;
+    return NDQ_OK;
+}
 
 extern "C" int ndq_set_launch_for(int sprec, int lprec, int recon, int block, int xcd_remap) {
     if (sprec < NDQ_F64 || sprec > NDQ_F16 || lprec < NDQ_F64 || lprec > NDQ_F16 ||

@@ -51,6 +51,7 @@ int sign_apply(DOp& d, const ndq_spinor* in) {
     d.ar->overflow = false;
     ndq_stats s;
     memset(&s, 0, sizeof(s));
+    d.S.nrhs = in->nrhs;   // S has room for the largest block
     int rc = apply_sign(d.g, d.U, d.p, in, &d.S, *d.ar, &s, d.st);
     d.stats->q_applies += s.q_applies;
     return rc;
@@ -272,6 +273,16 @@ int dh_apply(DOp& d, const ndq_spinor* y, const ndq_spinor* tmp, const ndq_spino
     return lincomb(d.g, d.prec, out, 2, src, cf, nullptr, nullptr, d.st);
 }
 
+// Inner relative residual when the caller leaves it open: half the target in
+// plain FP64; 1e-5 for F32 storage; for F16 storage (11-bit significands with
+// a per-site scale) eight units of its rounding, 8 * 2^-11, about where the
+// rounding of the stored vectors stops the inner CG from converging further.
+double default_inner_tol(int lo, double tol) {
+    if (lo == NDQ_F64) return 0.5 * tol;
+    if (lo == NDQ_F16) return 8.0 * 0x1p-11;
+    return 1e-5;
+}
+
 // |x_r|^2 of every field of a block, to the host (nr values).
 int host_norms(const ndq_geom* g, const ndq_spinor* x, double* partials, double* dscal, double* out, hipStream_t st) {
     int rc = dot(g, x, nullptr, partials, dscal, st);
@@ -283,85 +294,130 @@ int host_norms(const ndq_geom* g, const ndq_spinor* x, double* partials, double*
     return NDQ_OK;
 }
 
+// Field views of a block: the first n fields, and field k alone.
+ndq_spinor first(const ndq_spinor& b, int n) {
+    ndq_spinor o = b;
+    o.nrhs = n;
+    return o;
+}
+
+// dst field kd = c * src field ks (one field; c = 0 clears it).
+int copy_field(const ndq_geom* g, int prec, const ndq_spinor* dst, int kd, const ndq_spinor* src, int ks, double c,
+               hipStream_t st) {
+    const ndq_spinor d1 = rhs_slice(g, dst, kd), s1 = rhs_slice(g, src, ks);
+    const ndq_spinor* v[1] = {&s1};
+    const Coef cf[1] = {hc(c)};
+    return lincomb(g, prec, &d1, c == 0.0 ? 0 : 1, v, cf, nullptr, nullptr, st);
+}
+
 // CGNE for D e_r = rhs_r on every field r of a block at once: one D (or D^H)
-// application of the whole block per step, so that each sign application is
-// shared (links loaded once per stencil tile for all fields), and scalars per
-// field.  A field stops (its coefficients become those of the identity) once
-// its residual is below tol |rhs_r|, or from the start if active[r] is 0;
-// e starts at zero.  Returns the number of block iterations.
-int cgne_block(DOp& d, const ndq_spinor* rhs, Vecs& v, double tol, int max_iter, const int* active, double* partials,
-               double* dscal, int* iters) {
+// application of the block per step, so that each sign application is shared
+// (links loaded once per stencil tile for all fields), and scalars per field.
+// A field leaves the block once its residual is below tol |rhs_r|: its e is
+// written to eout (at its index in rhs), and the fields still running are
+// moved to the front, so every application of D works on those only.  Returns
+// the number of block iterations.
+int cgne_block(DOp& d, const ndq_spinor* rhs, Vecs& v, const ndq_spinor* eout, double tol, int max_iter,
+               double* partials, double* dscal, int* iters) {
     const ndq_geom* g = d.g;
     hipStream_t st = d.st;
-    const int nr = rhs->nrhs;
+    const int prec = d.prec;
+    int nb = rhs->nrhs;
     int rc;
     double r0[NDQ_MAX_BATCH], ss[NDQ_MAX_BATCH], zz[NDQ_MAX_BATCH], qq[NDQ_MAX_BATCH], zn[NDQ_MAX_BATCH];
     double cf[2 * NDQ_MAX_BATCH];
-    int act[NDQ_MAX_BATCH];
-    if ((rc = lincomb(g, d.prec, &v.e, 0, nullptr, nullptr, nullptr, nullptr, st))) return rc;
+    int orig[NDQ_MAX_BATCH], done[NDQ_MAX_BATCH];
+    for (int k = 0; k < nb; ++k) orig[k] = k;
+    *iters = 0;
+    // Write finished fields out and move the others to the front (vectors of
+    // the listed kinds and the per-field scalars).
+    auto compact = [&](bool move_p) -> int {
+        int w = 0;
+        for (int k = 0; k < nb; ++k) {
+            if (done[k]) {
+                int e2;
+                if ((e2 = copy_field(g, prec, eout, orig[k], &v.e, k, 1.0, st))) return e2;
+                continue;
+            }
+            if (w != k) {
+                int e2;
+                if ((e2 = copy_field(g, prec, &v.e, w, &v.e, k, 1.0, st))) return e2;
+                if ((e2 = copy_field(g, prec, &v.s, w, &v.s, k, 1.0, st))) return e2;
+                if (move_p && (e2 = copy_field(g, prec, &v.p, w, &v.p, k, 1.0, st))) return e2;
+                orig[w] = orig[k];
+                r0[w] = r0[k];
+                zz[w] = zz[k];
+                ss[w] = ss[k];
+            }
+            ++w;
+        }
+        nb = w;
+        return NDQ_OK;
+    };
+    ndq_spinor e = first(v.e, nb), s = first(v.s, nb);
+    if ((rc = lincomb(g, prec, &e, 0, nullptr, nullptr, nullptr, nullptr, st))) return rc;
     {
         const ndq_spinor* src[1] = {rhs};
         const Coef c1[1] = {hc(1.0)};
-        if ((rc = lincomb(g, d.prec, &v.s, 1, src, c1, nullptr, nullptr, st))) return rc;
+        if ((rc = lincomb(g, prec, &s, 1, src, c1, nullptr, nullptr, st))) return rc;
     }
-    if ((rc = host_norms(g, &v.s, partials, dscal, r0, st))) return rc;
-    int nact = 0;
-    for (int r = 0; r < nr; ++r) {
-        act[r] = active[r] && r0[r] > 0.0;
-        nact += act[r];
+    if ((rc = host_norms(g, &s, partials, dscal, r0, st))) return rc;
+    for (int k = 0; k < nb; ++k) {
+        done[k] = !(r0[k] > 0.0);
+        zz[k] = ss[k] = 0.0;
     }
-    *iters = 0;
-    if (!nact) return NDQ_OK;
+    if ((rc = compact(false))) return rc;
+    if (nb == 0) return NDQ_OK;
     // z = D^H s, p = z
-    if ((rc = dh_apply(d, &v.s, &v.t, &v.z))) return rc;
     {
-        const ndq_spinor* src[1] = {&v.z};
+        const ndq_spinor sb = first(v.s, nb), zb = first(v.z, nb), tb = first(v.t, nb), pb = first(v.p, nb);
+        if ((rc = dh_apply(d, &sb, &tb, &zb))) return rc;
+        const ndq_spinor* src[1] = {&zb};
         const Coef c1[1] = {hc(1.0)};
-        if ((rc = lincomb(g, d.prec, &v.p, 1, src, c1, nullptr, nullptr, st))) return rc;
+        if ((rc = lincomb(g, prec, &pb, 1, src, c1, nullptr, nullptr, st))) return rc;
+        if ((rc = host_norms(g, &zb, partials, dscal, zz, st))) return rc;
     }
-    if ((rc = host_norms(g, &v.z, partials, dscal, zz, st))) return rc;
     int it = 0;
-    while (it < max_iter && nact > 0) {
-        if ((rc = d_apply(d, &v.p, &v.q))) return rc;
-        if ((rc = host_norms(g, &v.q, partials, dscal, qq, st))) return rc;
+    while (it < max_iter && nb > 0) {
+        const ndq_spinor eb = first(v.e, nb), sb = first(v.s, nb), pb = first(v.p, nb), qb = first(v.q, nb);
+        if ((rc = d_apply(d, &pb, &qb))) return rc;
+        if ((rc = host_norms(g, &qb, partials, dscal, qq, st))) return rc;
         // e += alpha p, s -= alpha q
-        for (int r = 0; r < nr; ++r) {
-            if (act[r] && !(qq[r] > 0.0)) act[r] = 0;
-            const double alpha = act[r] ? zz[r] / qq[r] : 0.0;
-            cf[r] = 1.0;
-            cf[nr + r] = alpha;
+        for (int k = 0; k < nb; ++k) {
+            cf[k] = 1.0;
+            cf[nb + k] = qq[k] > 0.0 ? zz[k] / qq[k] : 0.0;
         }
         {
-            const ndq_spinor* src[2] = {&v.e, &v.p};
-            if ((rc = lincomb_rhs(g, d.prec, &v.e, 2, src, cf, nullptr, nullptr, st))) return rc;
-            for (int r = 0; r < nr; ++r) cf[nr + r] = -cf[nr + r];
-            const ndq_spinor* src2[2] = {&v.s, &v.q};
-            if ((rc = lincomb_rhs(g, d.prec, &v.s, 2, src2, cf, nullptr, nullptr, st))) return rc;
+            const ndq_spinor* src[2] = {&eb, &pb};
+            if ((rc = lincomb_rhs(g, prec, &eb, 2, src, cf, nullptr, nullptr, st))) return rc;
+            for (int k = 0; k < nb; ++k) cf[nb + k] = -cf[nb + k];
+            const ndq_spinor* src2[2] = {&sb, &qb};
+            if ((rc = lincomb_rhs(g, prec, &sb, 2, src2, cf, nullptr, nullptr, st))) return rc;
         }
-        if ((rc = host_norms(g, &v.s, partials, dscal, ss, st))) return rc;
+        if ((rc = host_norms(g, &sb, partials, dscal, ss, st))) return rc;
         ++it;
-        nact = 0;
-        for (int r = 0; r < nr; ++r) {
-            if (act[r] && ss[r] <= tol * tol * r0[r]) act[r] = 0;
-            nact += act[r];
+        bool any = false;
+        for (int k = 0; k < nb; ++k) {
+            done[k] = ss[k] <= tol * tol * r0[k] || !(qq[k] > 0.0);
+            any |= done[k] != 0;
         }
-        if (!nact) break;
-        // z = D^H s, p = z + beta p (stopped fields keep p)
-        if ((rc = dh_apply(d, &v.s, &v.t, &v.z))) return rc;
-        if ((rc = host_norms(g, &v.z, partials, dscal, zn, st))) return rc;
-        for (int r = 0; r < nr; ++r) {
-            if (act[r]) {
-                cf[r] = 1.0;
-                cf[nr + r] = zn[r] / zz[r];
-                zz[r] = zn[r];
-            } else {
-                cf[r] = 0.0;
-                cf[nr + r] = 1.0;
-            }
+        if (any && (rc = compact(true))) return rc;
+        if (nb == 0) break;
+        // z = D^H s, p = z + beta p
+        const ndq_spinor sc = first(v.s, nb), zc = first(v.z, nb), tc = first(v.t, nb), pc = first(v.p, nb);
+        if ((rc = dh_apply(d, &sc, &tc, &zc))) return rc;
+        if ((rc = host_norms(g, &zc, partials, dscal, zn, st))) return rc;
+        for (int k = 0; k < nb; ++k) {
+            cf[k] = 1.0;
+            cf[nb + k] = zn[k] / zz[k];
+            zz[k] = zn[k];
         }
-        const ndq_spinor* src[2] = {&v.z, &v.p};
-        if ((rc = lincomb_rhs(g, d.prec, &v.p, 2, src, cf, nullptr, nullptr, st))) return rc;
+        const ndq_spinor* src[2] = {&zc, &pc};
+        if ((rc = lincomb_rhs(g, prec, &pc, 2, src, cf, nullptr, nullptr, st))) return rc;
     }
+    // fields stopped by the iteration limit
+    for (int k = 0; k < nb; ++k)
+        if ((rc = copy_field(g, prec, eout, orig[k], &v.e, k, 1.0, st))) return rc;
     *iters = it;
     return NDQ_OK;
 }
@@ -428,7 +484,7 @@ int solve_single(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, 
     }
     const int max_outer = sp->max_outer > 0 ? sp->max_outer : 20;
     const int max_inner = sp->max_inner > 0 ? sp->max_inner : 100000;
-    const double inner_tol = sp->inner_tol > 0 ? sp->inner_tol : (lo == NDQ_F64 ? 0.5 * sp->tol : 1e-5);
+    const double inner_tol = sp->inner_tol > 0 ? sp->inner_tol : default_inner_tol(lo, sp->tol);
     double rr = 0.0;
     for (int outer = 0;; ++outer) {
         // r = b - D x (FP64)
@@ -504,7 +560,7 @@ int solve_block(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, c
     const ndq_overlap_params* pi = lo == NDQ_F64 ? p64 : plo;
     Arena ar{static_cast<char*>(ws), ws_bytes};
     ndq_spinor r = ws_block(ar, g, NDQ_F64, nr), t64 = ws_block(ar, g, NDQ_F64, nr), S64 = ws_block(ar, g, NDQ_F64, nr);
-    ndq_spinor rlo = ws_block(ar, g, lo, nr), Slo = ws_block(ar, g, lo, nr);
+    ndq_spinor rlo = ws_block(ar, g, lo, nr), Slo = ws_block(ar, g, lo, nr), Eo = ws_block(ar, g, lo, nr);
     Vecs v{ws_block(ar, g, lo, nr), ws_block(ar, g, lo, nr), ws_block(ar, g, lo, nr), ws_block(ar, g, lo, nr),
            ws_block(ar, g, lo, nr), ws_block(ar, g, lo, nr)};
     double* partials = static_cast<double*>(ar.take(partials_capacity(g, 2 * nr)));
@@ -529,7 +585,7 @@ int solve_block(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, c
     }
     const int max_outer = sp->max_outer > 0 ? sp->max_outer : 20;
     const int max_inner = sp->max_inner > 0 ? sp->max_inner : 100000;
-    const double inner_tol = sp->inner_tol > 0 ? sp->inner_tol : (lo == NDQ_F64 ? 0.5 * sp->tol : 1e-5);
+    const double inner_tol = sp->inner_tol > 0 ? sp->inner_tol : default_inner_tol(lo, sp->tol);
     for (int outer = 0;; ++outer) {
         // r = b - D x (FP64)
         if ((rc = d_apply(d64, x, &t64))) return rc;
@@ -551,30 +607,36 @@ int solve_block(const ndq_geom* g, const ndq_gauge* U64, const ndq_gauge* Ulo, c
         if (!nact) break;
         if (outer >= max_outer)
             return fail(NDQ_ENOCONV, "solve: largest residual %.3e after %d outer steps", worst, outer);
-        // r_lo = r / |r| on the fields still above the target, zero elsewhere
-        for (int j = 0; j < nr; ++j) cf[j] = act[j] ? 1.0 / rn[j] : 0.0;
-        const ndq_spinor* s1[1] = {&r};
+        // the fields still above the target, r_lo = r / |r|, moved to the front
+        int idx[NDQ_MAX_BATCH];
+        int na = 0;
+        for (int j = 0; j < nr; ++j)
+            if (act[j]) idx[na++] = j;
+        for (int k = 0; k < na; ++k)
+            if ((rc = copy_field(g, NDQ_F64, &t64, k, &r, idx[k], 1.0 / rn[idx[k]], st))) return rc;
+        const ndq_spinor rl = first(rlo, na), tl = first(t64, na), el = first(Eo, na);
         if (lo == NDQ_F64) {
-            if ((rc = lincomb_rhs(g, NDQ_F64, &rlo, 1, s1, cf, nullptr, nullptr, st))) return rc;
-        } else {
-            if ((rc = lincomb_rhs(g, NDQ_F64, &t64, 1, s1, cf, nullptr, nullptr, st))) return rc;
-            if ((rc = convert(g, &rlo, &t64, st))) return rc;
+            const ndq_spinor* s1[1] = {&tl};
+            const Coef c1[1] = {Coef{1.0, nullptr}};
+            if ((rc = lincomb(g, NDQ_F64, &rl, 1, s1, c1, nullptr, nullptr, st))) return rc;
+        } else if ((rc = convert(g, &rl, &tl, st))) {
+            return rc;
         }
         int its = 0;
-        if ((rc = cgne_block(dlo, &rlo, v, inner_tol, max_inner, act, partials, dscal, &its))) return rc;
+        if ((rc = cgne_block(dlo, &rl, v, &el, inner_tol, max_inner, partials, dscal, &its))) return rc;
         stt->inner += its;
-        const ndq_spinor* ex = &v.e;
+        const ndq_spinor* ex = &el;
         if (lo != NDQ_F64) {
-            if ((rc = convert(g, &t64, &v.e, st))) return rc;
-            ex = &t64;
+            if ((rc = convert(g, &tl, &el, st))) return rc;
+            ex = &tl;
         }
         // x += |r| e
-        for (int j = 0; j < nr; ++j) {
-            cf[j] = 1.0;
-            cf[nr + j] = act[j] ? rn[j] : 0.0;
+        for (int k = 0; k < na; ++k) {
+            const ndq_spinor xk = rhs_slice(g, x, idx[k]), ek = rhs_slice(g, ex, k);
+            const ndq_spinor* s2[2] = {&xk, &ek};
+            const Coef c2[2] = {Coef{1.0, nullptr}, Coef{rn[idx[k]], nullptr}};
+            if ((rc = lincomb(g, NDQ_F64, &xk, 2, s2, c2, nullptr, nullptr, st))) return rc;
         }
-        const ndq_spinor* s2[2] = {x, ex};
-        if ((rc = lincomb_rhs(g, NDQ_F64, x, 2, s2, cf, nullptr, nullptr, st))) return rc;
     }
     return NDQ_OK;
 }
@@ -600,7 +662,7 @@ size_t ndq_solve_workspace_bytes_nrhs(const ndq_geom* g, const ndq_overlap_param
     const int nr = sp->sectors ? 1 : nrhs;
     size_t b = 0;
     b += 3 * ((size_t)spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL) * nr + 256);   // r, t64, S64
-    b += 8 * ((size_t)spinor_rhs_bytes(g, lo, NDQ_FULL) * nr + 256);        // r_lo, S_lo, e s z p q t
+    b += 9 * ((size_t)spinor_rhs_bytes(g, lo, NDQ_FULL) * nr + 256);        // r_lo, S_lo, e_out, e s z p q t
     b += partials_capacity(g, 2 * nr) + (64 + 2 * nr) * sizeof(double) + 1024;
     const size_t s64 = sign_workspace(g, p64, NDQ_F64, nr);
     const size_t slo = sign_workspace(g, pi, lo, nr);

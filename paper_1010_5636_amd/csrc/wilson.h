@@ -61,6 +61,23 @@ struct Tuning {
 Tuning& tuning(int sprec, int lprec, int recon);
 inline int recon_index(int recon) { return recon == 18 ? 0 : recon == 12 ? 1 : 2; }
 
+// Work order of the multi-right-hand-side stencil (see k_wilson_mrhs): rg
+// right-hand sides per workgroup (0: all), group-major or tile-major order of
+// the groups, tile-order chunk (-1: tile_order's choice, 0: index order), XCD
+// remap.  Looked up per (lattice, spinor precision, link precision, recon,
+// nrhs, output parities); set by ndq_set_mrhs_launch or the autotuner, else
+// the default below.
+struct MrhsShape {
+    int rg = 0;
+    int group_major = 0;
+    int chunk = -1;
+    int xcd_remap = 1;
+    int link_nt = -1;    // links loaded with the non-temporal hint: -1 automatic, 0 no, 1 yes
+};
+MrhsShape mrhs_shape(const GeomK& g, int sprec, int lprec, int recon, int nrhs, int ny);
+void set_mrhs_shape(const GeomK& g, int sprec, int lprec, int recon, int nrhs, int ny, const MrhsShape& s);
+MrhsShape default_mrhs_shape(const GeomK& g, int sprec, int lprec, int recon, int nrhs, int ny);
+
 WilsonArgs wilson_args(const ndq_geom* g, const ndq_gauge* U, int sprec);
 int wilson_blocks(const ndq_geom* g, int block, int ny);
 hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& a, int ny, int block, hipStream_t st);

@@ -416,14 +416,15 @@ __global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
 // arithmetic is that of k_wilson (same hop order and epilogue), so results
 // match the one-lane-per-site kernel bit for bit.
 //
-// One tile: output parity p, sites 64*tile .. 64*tile+63 of that parity.  The
-// views address right-hand side 0; right-hand side r sits r * rhs_bytes
-// further.  `self` may be null (no same-site term).  Must be reached by all
-// 256 threads of the workgroup (it synchronises once).
+// One tile: output parity p, sites 64*tile .. 64*tile+63 of that parity, and
+// right-hand sides r0 .. r1-1.  The views address right-hand side 0;
+// right-hand side r sits r * rhs_bytes further.  `self` may be null (no
+// same-site term).  Must be reached by all 256 threads of the workgroup (it
+// synchronises once).
 template <int SP, int LP, int RECON, bool NT>
 __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int p, int32_t tile,
                                           const SpinorView& in, const SpinorView* self, const SpinorView& out,
-                                          double a_self, double b_hop, int gamma5, double c0d, int nrhs,
+                                          double a_self, double b_hop, int gamma5, double c0d, int r0, int r1,
                                           uint32_t* lw, int nv = 0, const SpinorView* v = nullptr,
                                           const double* cvd = nullptr) {
     using R = typename SpinorIO<SP>::R;
@@ -448,7 +449,7 @@ __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int
     __syncthreads();
     if (!active) return;
 #pragma unroll 1
-    for (int r = w; r < nrhs; r += 4) {
+    for (int r = r0 + w; r < r1; r += 4) {
         // re-read links from LDS for every right-hand side instead of letting
         // them be hoisted into registers (which would cost occupancy)
         int lo = lane;
@@ -522,13 +523,44 @@ __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int
     }
 }
 
+// Work order of the multi-right-hand-side launch: a 1-D grid of tiles x ny
+// output parities x ngroups groups of `rg` right-hand sides.  Group-major
+// order runs every tile for one group before the next group (the spinors
+// re-read by neighbouring tiles are then those of rg fields only, so they stay
+// in L2; links are read once per group); tile-major order runs the groups of a
+// tile next to each other (they share the tile's links in L2).
+struct MrhsGrid {
+    int32_t tiles;       // tiles of 64 sites per parity
+    int ny;              // output parities (1 or 2)
+    int rg;              // right-hand sides per workgroup
+    int ngroups;
+    int group_major;
+    int nrhs;
+};
+
 template <int SP, int LP, int RECON, bool NT>
-__global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, int nrhs) {
+__global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, MrhsGrid m) {
     extern __shared__ uint32_t lw[];   // [8 dirs][link words][64 sites]
-    unsigned lin = blockIdx.y * gridDim.x + blockIdx.x;
-    if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x * gridDim.y);
-    int y;
-    const int32_t tile = order_tile(parity_slot(lin, y), (int32_t)gridDim.x, a.g.n0, a.order_c);
+    unsigned lin = blockIdx.x;
+    if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x);
+    const unsigned per_group = (unsigned)(m.ny * m.tiles);
+    unsigned grp, rem;
+    if (m.group_major) {
+        grp = lin / per_group;
+        rem = lin - grp * per_group;
+    } else {
+        rem = lin / (unsigned)m.ngroups;
+        grp = lin - rem * (unsigned)m.ngroups;
+    }
+    int y = 0;
+    int32_t pos = (int32_t)rem;
+    if (m.ny == 2) {
+        y = (int)(rem & 1u);
+        pos = (int32_t)(rem >> 1);
+    }
+    const int32_t tile = order_tile(pos, m.tiles, a.g.n0, a.order_c);
+    const int r0 = (int)grp * m.rg;
+    const int r1 = min(m.nrhs, r0 + m.rg);
     SpinorView vv[3];
     double cv[3];
     for (int j = 0; j < a.nv; ++j) {
@@ -536,7 +568,7 @@ __global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, int nrhs) {
         cv[j] = coef(a.cv[j]);
     }
     mrhs_tile<SP, LP, RECON, NT>(a.g, a.links, a.p0 + y, tile, a.in[y], a.has_self ? &a.self[y] : nullptr, a.out[y],
-                                 a.a_self, a.b_hop, a.gamma5, coef(a.c0), nrhs, lw, a.nv, vv, cv);
+                                 a.a_self, a.b_hop, a.gamma5, coef(a.c0), r0, r1, lw, a.nv, vv, cv);
 }
 
 template <int SP, int LP, int RECON>
@@ -554,20 +586,21 @@ hipError_t allow_lds(K kernel, size_t lds) {
 }
 
 template <int SP, int LP, int RECON, bool NT>
-hipError_t launch_mrhs_nt(const WilsonArgs& a, int ny, int nrhs, hipStream_t st) {
-    const dim3 grid((unsigned)((a.g.vh + 63) / 64), ny);
+hipError_t launch_mrhs_nt(const WilsonArgs& a, const MrhsGrid& m, hipStream_t st) {
+    const dim3 grid((unsigned)((int64_t)m.tiles * m.ny * m.ngroups));
     const size_t lds = mrhs_lds_bytes<SP, LP, RECON>();
     const hipError_t e = allow_lds(&k_wilson_mrhs<SP, LP, RECON, NT>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_wilson_mrhs<SP, LP, RECON, NT>), grid, dim3(256), lds, st, a, nrhs);
+    hipLaunchKernelGGL((k_wilson_mrhs<SP, LP, RECON, NT>), grid, dim3(256), lds, st, a, m);
     return hipGetLastError();
 }
 
-// one output parity (ny = 1) reads every link once: non-temporal link loads
+// non-temporal link loads (automatic: when every link is read once, i.e. one
+// output parity (ny = 1) and one group of right-hand sides)
 template <int SP, int LP, int RECON>
-hipError_t launch_mrhs_fmt(const WilsonArgs& a, int ny, int nrhs, hipStream_t st) {
-    return ny == 1 ? launch_mrhs_nt<SP, LP, RECON, true>(a, ny, nrhs, st)
-                   : launch_mrhs_nt<SP, LP, RECON, false>(a, ny, nrhs, st);
+hipError_t launch_mrhs_fmt(const WilsonArgs& a, const MrhsGrid& m, int link_nt, hipStream_t st) {
+    const bool nt = link_nt < 0 ? (m.ny == 1 && m.ngroups == 1) : link_nt != 0;
+    return nt ? launch_mrhs_nt<SP, LP, RECON, true>(a, m, st) : launch_mrhs_nt<SP, LP, RECON, false>(a, m, st);
 }
 
 // Q on several lattices (each with its own links and right-hand sides) in one
@@ -592,7 +625,7 @@ __global__ void __launch_bounds__(256) k_wilson_multi(MultiArgs a) {
         const int y = local / J.tiles;
         const int32_t tile = local - y * J.tiles;
         mrhs_tile<SP, LP, RECON, false>(J.g, J.links, y, tile, J.in[y], &J.self[y], J.out[y], J.a_self, -0.5, 1, 1.0,
-                                 J.nrhs, lw);
+                                        0, J.nrhs, lw);
         __syncthreads();   // the next tile overwrites the staged links
     }
 }
@@ -680,22 +713,31 @@ hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& args
 hipError_t launch_wilson_mrhs(int sprec, int lprec, int recon, const WilsonArgs& args, int ny, int nrhs,
                               hipStream_t st) {
     WilsonArgs a = args;
-    a.order_c = tile_order(a.g, 64);
+    const MrhsShape sh = mrhs_shape(args.g, sprec, lprec, recon, nrhs, ny);
+    a.order_c = sh.chunk < 0 ? tile_order(a.g, 64) : sh.chunk;
+    a.xcd_remap = sh.xcd_remap;
+    MrhsGrid m;
+    m.tiles = (a.g.vh + 63) / 64;
+    m.ny = ny;
+    m.rg = std::max(1, std::min(sh.rg > 0 ? sh.rg : nrhs, nrhs));
+    m.ngroups = (nrhs + m.rg - 1) / m.rg;
+    m.group_major = sh.group_major;
+    m.nrhs = nrhs;
     const int key = sprec * 1000 + lprec * 100 + recon;
     switch (key) {
-        case P64 * 1000 + P64 * 100 + 18: return launch_mrhs_fmt<P64, P64, 18>(a, ny, nrhs, st);
-        case P64 * 1000 + P64 * 100 + 12: return launch_mrhs_fmt<P64, P64, 12>(a, ny, nrhs, st);
-        case P64 * 1000 + P64 * 100 + 8: return launch_mrhs_fmt<P64, P64, 8>(a, ny, nrhs, st);
-        case P32 * 1000 + P32 * 100 + 18: return launch_mrhs_fmt<P32, P32, 18>(a, ny, nrhs, st);
-        case P32 * 1000 + P32 * 100 + 12: return launch_mrhs_fmt<P32, P32, 12>(a, ny, nrhs, st);
-        case P32 * 1000 + P32 * 100 + 8: return launch_mrhs_fmt<P32, P32, 8>(a, ny, nrhs, st);
-        case P32 * 1000 + P16 * 100 + 18: return launch_mrhs_fmt<P32, P16, 18>(a, ny, nrhs, st);
-        case P32 * 1000 + P16 * 100 + 12: return launch_mrhs_fmt<P32, P16, 12>(a, ny, nrhs, st);
-        case P16 * 1000 + P32 * 100 + 18: return launch_mrhs_fmt<P16, P32, 18>(a, ny, nrhs, st);
-        case P16 * 1000 + P32 * 100 + 12: return launch_mrhs_fmt<P16, P32, 12>(a, ny, nrhs, st);
-        case P16 * 1000 + P32 * 100 + 8: return launch_mrhs_fmt<P16, P32, 8>(a, ny, nrhs, st);
-        case P16 * 1000 + P16 * 100 + 18: return launch_mrhs_fmt<P16, P16, 18>(a, ny, nrhs, st);
-        case P16 * 1000 + P16 * 100 + 12: return launch_mrhs_fmt<P16, P16, 12>(a, ny, nrhs, st);
+        case P64 * 1000 + P64 * 100 + 18: return launch_mrhs_fmt<P64, P64, 18>(a, m, sh.link_nt, st);
+        case P64 * 1000 + P64 * 100 + 12: return launch_mrhs_fmt<P64, P64, 12>(a, m, sh.link_nt, st);
+        case P64 * 1000 + P64 * 100 + 8: return launch_mrhs_fmt<P64, P64, 8>(a, m, sh.link_nt, st);
+        case P32 * 1000 + P32 * 100 + 18: return launch_mrhs_fmt<P32, P32, 18>(a, m, sh.link_nt, st);
+        case P32 * 1000 + P32 * 100 + 12: return launch_mrhs_fmt<P32, P32, 12>(a, m, sh.link_nt, st);
+        case P32 * 1000 + P32 * 100 + 8: return launch_mrhs_fmt<P32, P32, 8>(a, m, sh.link_nt, st);
+        case P32 * 1000 + P16 * 100 + 18: return launch_mrhs_fmt<P32, P16, 18>(a, m, sh.link_nt, st);
+        case P32 * 1000 + P16 * 100 + 12: return launch_mrhs_fmt<P32, P16, 12>(a, m, sh.link_nt, st);
+        case P16 * 1000 + P32 * 100 + 18: return launch_mrhs_fmt<P16, P32, 18>(a, m, sh.link_nt, st);
+        case P16 * 1000 + P32 * 100 + 12: return launch_mrhs_fmt<P16, P32, 12>(a, m, sh.link_nt, st);
+        case P16 * 1000 + P32 * 100 + 8: return launch_mrhs_fmt<P16, P32, 8>(a, m, sh.link_nt, st);
+        case P16 * 1000 + P16 * 100 + 18: return launch_mrhs_fmt<P16, P16, 18>(a, m, sh.link_nt, st);
+        case P16 * 1000 + P16 * 100 + 12: return launch_mrhs_fmt<P16, P16, 12>(a, m, sh.link_nt, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -176,6 +176,9 @@ _SIG = {
     "ndq_gauge_force": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P, _P,
                              _P]),
     "ndq_set_launch": (_I, [_I, _I]),
+    "ndq_set_mrhs_launch": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _I, _I]),
+    "ndq_get_mrhs_launch": (_I, [_P, _I, _I, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
+                                 ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "ndq_set_launch_for": (_I, [_I, _I, _I, _I, _I]),
 }
 
@@ -238,6 +241,20 @@ def get_launch(sprec: int, lprec: int, recon: int) -> dict:
     x = ctypes.c_int()
     _check(lib().ndq_get_launch_for(sprec, lprec, recon, ctypes.byref(b), ctypes.byref(x)))
     return {"block": b.value, "xcd_remap": x.value}
+
+
+def set_mrhs_launch(geom: "Geometry", sprec: int, lprec: int, recon: int, nrhs: int, ny: int, rg: int = 0,
+                    group_major: bool = False, chunk: int = -1, xcd_remap: bool = True, link_nt: int = -1):
+    """Work order of the multi-right-hand-side stencil for one lattice, format, nrhs and ny."""
+    _check(lib().ndq_set_mrhs_launch(geom.handle, sprec, lprec, recon, nrhs, ny, rg, int(bool(group_major)), chunk,
+                                     int(bool(xcd_remap)), int(link_nt)))
+
+
+def get_mrhs_launch(geom: "Geometry", sprec: int, lprec: int, recon: int, nrhs: int, ny: int) -> dict:
+    v = [ctypes.c_int() for _ in range(5)]
+    _check(lib().ndq_get_mrhs_launch(geom.handle, sprec, lprec, recon, nrhs, ny, *[ctypes.byref(x) for x in v]))
+    return {"rg": v[0].value, "group_major": v[1].value, "chunk": v[2].value, "xcd_remap": v[3].value,
+            "link_nt": v[4].value}
 
 
 def set_launch_for(sprec: int, lprec: int, recon: int, block: int, xcd_remap: bool = True):

@@ -150,3 +150,36 @@ def test_point_sources_32c64():
     # nothing leaks beyond the 9 sites: the total norm is the norm at those sites
     total = torch.linalg.vector_norm(out).item()
     assert abs(total - np.linalg.norm(got)) <= 1e-12 * total
+
+
+@pytest.mark.parametrize("shape", [(0, 0, -1, 1, -1), (1, 1, 0, 1, -1), (3, 1, 2, 0, 1), (5, 0, 4, 1, 0),
+                                   (6, 1, 4, 1, -1), (12, 1, 8, 1, 1)])
+def test_work_order_does_not_change_results(shape):
+    """Every work order of the multi-RHS stencil (fields per workgroup, group-
+    or tile-major order, tile chunk, XCD remap, link load hint) gives the same
+    bits: 12 fields of Q on an 8x8x8x16 lattice (8 tiles of 64 sites per time
+    slice; ragged last group for 5 per group), and the even/odd hopping block
+    on the same fields."""
+    rg, gm, chunk, xcd, nt = shape
+    dims = (8, 8, 8, 16)
+    g = ndq.Geometry(dims)
+    v = g.volume
+    U = ndq.GaugeField.pack(g, cu(synthetic.gauge_field(dims, seed=5)), ndq.F32, 12)
+    psi = synthetic.spinor(v, nrhs=12, seed=6)
+    x = ndq.SpinorField.pack(g, cu(psi), ndq.F32, ndq.FULL)
+    xo = ndq.SpinorField.pack(g, cu(psi[:, : v // 2]), ndq.F32, ndq.ODD)
+    outs = {}
+    for label, sh in (("default", None), ("shape", shape)):
+        if sh is not None:
+            ndq.ndq.set_mrhs_launch(g, ndq.F32, ndq.F32, 12, 12, 2, rg, bool(gm), chunk, bool(xcd), nt)
+            ndq.ndq.set_mrhs_launch(g, ndq.F32, ndq.F32, 12, 12, 1, rg, bool(gm), chunk, bool(xcd), nt)
+        y = x.like()
+        ndq.apply_Q(g, U, M, x, y)
+        ye = xo.like(parity=ndq.EVEN)
+        ndq.apply_dslash(g, U, xo, ye)
+        torch.cuda.synchronize()
+        outs[label] = (y.buf.clone(), ye.buf.clone())
+    got = ndq.ndq.get_mrhs_launch(g, ndq.F32, ndq.F32, 12, 12, 2)
+    assert (got["rg"], got["group_major"], got["chunk"], got["xcd_remap"]) == (rg, gm, chunk, xcd)
+    assert torch.equal(outs["default"][0], outs["shape"][0])
+    assert torch.equal(outs["default"][1], outs["shape"][1])
