@@ -22,12 +22,12 @@
  *     massive operator D_N^m = (1 - abar mq/2) D_N + mq (the form bounded by Eq. 12).
  *
  * Memory and ownership:
- *   - every device buffer of a compute call is allocated and owned by the
- *     caller; *_bytes() queries give the sizes.  Only set-up utilities
- *     allocate: ndq_autotune (its rotating field copies, freed before it
- *     returns), ndq_gauge_pack for 8-real links (a 4-byte pinned host flag),
- *     and the graph replay of ndq_overlap_params.graph (a capture stream per
- *     device and up to four instantiated graphs per host thread);
+ *   - every device buffer is allocated and owned by the caller; *_bytes()
+ *     queries give the sizes (workspaces included).  The library allocates
+ *     no memory of its own, except the objects of the graph replay of
+ *     ndq_overlap_params.graph (a capture stream per device and up to four
+ *     instantiated graphs per host thread) and the static scratch of
+ *     ndq_apply_DN_noalloc;
  *   - "canonical" buffers are complex128 (interleaved re, im doubles) in device
  *     memory: gauge [V][4 mu][3 row][3 col] in lexicographic order; spinor
  *     [nrhs][nsites][4 spin][3 colour] with nsites = V (lexicographic order)
@@ -116,13 +116,17 @@ typedef struct {
     int32_t nrhs;
 } ndq_spinor;
 
+/* Bytes of a packed gauge field: 4V links of link_bytes(prec, recon), and for
+ * 8-real links a 256-byte status area after them (the singularity flag that
+ * ndq_gauge_pack reads back). */
 size_t ndq_gauge_bytes(const ndq_geom* g, int prec, int recon);
 size_t ndq_spinor_bytes(const ndq_geom* g, int prec, int parity, int nrhs);
 
 /* Convert a canonical complex128 gauge field (device) to the packed format.
  * Errors: NDQ_EPREC; NDQ_ESINGULAR (recon 8 and some link has
  * |a2|^2 + |a3|^2 < 1e-12, e.g. the unit field).  Synchronises `stream` for
- * recon 8 (to read back the singularity flag); otherwise asynchronous. */
+ * recon 8 (to read back the singularity flag from the field's status area);
+ * otherwise asynchronous. */
 int ndq_gauge_pack(const ndq_geom* g, const void* d_canon, const ndq_gauge* dst, void* stream);
 
 /* Reconstruct a packed gauge field into canonical complex128 (device). */
@@ -483,8 +487,11 @@ int ndq_get_launch_for(int sprec, int lprec, int recon, int* block, int* xcd_rem
  * rotating copies of (links, even spinor, odd spinor) so that consecutive
  * applies stream from HBM as in a solver (rotate_bytes <= 0: one set), and
  * records the fastest shape for that storage format as ndq_set_launch_for
- * does; the shape already in use is kept if it is within 3% of the fastest.  Allocates and frees its own device buffers; synchronises `stream`.
- * Errors: NDQ_EINVAL, NDQ_EPREC, NDQ_EHIP (the previous shape is kept). */
+ * does; the shape already in use is kept if it is within 3% of the fastest.
+ * The copies live in the caller's workspace ws of at least
+ * ndq_autotune_workspace_bytes(g, U, sprec, rotate_bytes) bytes (the first set
+ * uses U itself).  Synchronises `stream`.
+ * Errors: NDQ_EINVAL, NDQ_EPREC, NDQ_ENOMEM, NDQ_EHIP (the previous shape is kept). */
 typedef struct {
     int32_t block;        /* chosen shape                                            */
     int32_t xcd_remap;
@@ -492,8 +499,32 @@ typedef struct {
     double us[8];         /* every shape: index 2 * b + xcd_remap, b over 0/64/128/256 */
     int32_t nsets;        /* rotating sets used                                      */
 } ndq_tune_result;
-int ndq_autotune(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, int64_t rotate_bytes,
-                 ndq_tune_result* out, void* stream);
+size_t ndq_autotune_workspace_bytes(const ndq_geom* g, const ndq_gauge* U, int sprec, int64_t rotate_bytes);
+int ndq_autotune(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, int64_t rotate_bytes, void* ws,
+                 size_t ws_bytes, ndq_tune_result* out, void* stream);
+
+/* Autotuner of the multi-right-hand-side work order (see ndq_set_mrhs_launch)
+ * for lattice g, links U, spinor precision sprec, nrhs >= 2 fields and ny
+ * output parities (2: Q, 1: the even/odd hopping block): times `reps` applies
+ * of the order in use and of each candidate (fields per workgroup nrhs,
+ * nrhs/2, nrhs/3, 6, 4, 2; group- and tile-major; automatic, index-order and
+ * two-x1-row tile chunks) on a block of fields in ws (at least
+ * ndq_autotune_mrhs_workspace_bytes(g, sprec, nrhs, ny) bytes), and records the
+ * fastest, keeping the order in use unless another is more than 3% faster.
+ * If the environment variable NDQ_TUNE_CACHE names a file, an entry for this
+ * key found there is applied without timing (cached = 1) and a new result is
+ * appended to it (one text line per key).  Synchronises `stream`.
+ * Errors: NDQ_EINVAL, NDQ_EPREC, NDQ_ENOMEM, NDQ_EHIP. */
+typedef struct {
+    int32_t rg, group_major, chunk, xcd_remap, link_nt;   /* chosen order             */
+    int32_t nshapes;      /* candidates timed                                           */
+    int32_t cached;       /* 1: taken from NDQ_TUNE_CACHE                                */
+    double us_best;       /* time per apply of the chosen order, microseconds            */
+    double us_previous;   /* of the order in use before the call                         */
+} ndq_mrhs_tune_result;
+size_t ndq_autotune_mrhs_workspace_bytes(const ndq_geom* g, int sprec, int nrhs, int ny);
+int ndq_autotune_mrhs(const ndq_geom* g, const ndq_gauge* U, int sprec, int nrhs, int ny, int reps, void* ws,
+                      size_t ws_bytes, ndq_mrhs_tune_result* out, void* stream);
 
 /* Gram matrix of two blocks of fields, G[i][j] = <A_i, B_j> = sum over sites and
  * spin-colour components of conj(A_i) B_j (the inner products of the

@@ -165,6 +165,7 @@ int ndq_geom_tables(const ndq_geom* g, int32_t* d_nb, int32_t* d_lex_of_eo, int3
 
 size_t ndq_gauge_bytes(const ndq_geom* g, int prec, int recon) {
     if (!g || prec < NDQ_F64 || prec > NDQ_F16 || (recon != 18 && recon != 12 && recon != 8)) return 0;
+    if (recon == 8) return ndq::gauge_status_offset(g, prec, recon) + 256;
     return (size_t)g->volume * 4 * ndq::link_bytes(prec, recon);
 }
 

@@ -162,14 +162,12 @@ int ndq_gauge_pack(const ndq_geom* g, const void* d_canon, const ndq_gauge* dst,
     if (rc) return rc;
     hipStream_t st = as_stream(stream);
     char* links = static_cast<char*>(dst->data);
-    // recon 8: a pinned, device-mapped host word collects the singularity flag
-    // (the library allocates no device memory); lanes only ever store 1 to it.
+    // recon 8: the status word after the links (inside the caller's buffer,
+    // see ndq_gauge_bytes) collects the singularity flag; lanes only store 1
     int* flag = nullptr;
-    int* hflag = nullptr;
     if (dst->recon == 8) {
-        NDQ_HIP(hipHostMalloc((void**)&hflag, sizeof(int), hipHostMallocMapped));
-        *hflag = 0;
-        NDQ_HIP(hipHostGetDevicePointer((void**)&flag, hflag, 0));
+        flag = reinterpret_cast<int*>(links + gauge_status_offset(g, dst->prec, dst->recon));
+        NDQ_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
     }
     switch (dst->prec * 100 + dst->recon) {
         case NDQ_F64 * 100 + 18: rc = launch_gauge_pack<P64, 18>(g, d_canon, links, flag, st); break;
@@ -182,14 +180,11 @@ int ndq_gauge_pack(const ndq_geom* g, const void* d_canon, const ndq_gauge* dst,
         case NDQ_F16 * 100 + 12: rc = launch_gauge_pack<P16, 12>(g, d_canon, links, flag, st); break;
         default: rc = fail(NDQ_EPREC, "ndq_gauge_pack: unsupported format");
     }
-    if (hflag) {
-        if (rc == NDQ_OK) {
-            hipError_t e = hipStreamSynchronize(st);
-            if (e != hipSuccess) rc = fail(NDQ_EHIP, "ndq_gauge_pack: %s", hipGetErrorString(e));
-            else if (*(volatile int*)hflag)
-                rc = fail(NDQ_ESINGULAR, "8-real links are singular where |a2|^2 + |a3|^2 < 1e-12 (e.g. U = 1)");
-        }
-        hipHostFree(hflag);
+    if (flag && rc == NDQ_OK) {
+        int h = 0;
+        NDQ_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        NDQ_HIP(hipStreamSynchronize(st));
+        if (h) rc = fail(NDQ_ESINGULAR, "8-real links are singular where |a2|^2 + |a3|^2 < 1e-12 (e.g. U = 1)");
     }
     return rc;
 }

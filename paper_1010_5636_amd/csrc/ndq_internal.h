@@ -41,6 +41,12 @@ inline int64_t spinor_rhs_bytes(const ndq_geom* g, int prec, int parity) {
 
 inline int link_bytes(int prec, int recon) { return recon * (prec == NDQ_F64 ? 8 : prec == NDQ_F32 ? 4 : 2); }
 
+// Packed links: all 4V links, then (8-real links only) a 256-byte status area
+// whose first int is the singularity flag of the last ndq_gauge_pack.
+inline size_t gauge_status_offset(const ndq_geom* g, int prec, int recon) {
+    return ((size_t)g->volume * 4 * link_bytes(prec, recon) + 255) & ~size_t(255);
+}
+
 // Validate a spinor descriptor; `want_parity` < 0 accepts any subset.
 int check_spinor(const ndq_geom* g, const ndq_spinor* s, int want_parity, const char* name);
 int check_gauge(const ndq_gauge* u);

@@ -54,6 +54,15 @@ class _TuneResult(ctypes.Structure):
                 ("us", ctypes.c_double * 8), ("nsets", ctypes.c_int32)]
 
 
+class _MrhsTuneResult(ctypes.Structure):
+    _fields_ = [("rg", ctypes.c_int32), ("group_major", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32), ("link_nt", ctypes.c_int32), ("nshapes", ctypes.c_int32),
+                ("cached", ctypes.c_int32), ("us_best", ctypes.c_double), ("us_previous", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("m", ctypes.c_double), ("mq", ctypes.c_double), ("lam_max", ctypes.c_double),
                 ("approx", ctypes.c_void_p), ("modes", ctypes.c_void_p), ("nu", ctypes.POINTER(ctypes.c_double)),
@@ -136,8 +145,12 @@ _SIG = {
     "ndq_apply_Q": (_I, [_P, ctypes.POINTER(_Gauge), _D, ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P]),
     "ndq_get_launch_for": (_I, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int)]),
-    "ndq_autotune": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+    "ndq_autotune_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(_Gauge), ctypes.c_int, ctypes.c_int64]),
+    "ndq_autotune": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.c_int, ctypes.c_int, ctypes.c_int64, _P, ctypes.c_size_t,
                           ctypes.POINTER(_TuneResult), _P]),
+    "ndq_autotune_mrhs_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "ndq_autotune_mrhs": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P,
+                               ctypes.c_size_t, ctypes.POINTER(_MrhsTuneResult), _P]),
     "ndq_gram_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_int]),
     "ndq_spinor_gram": (_I, [_P, ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P, _P, ctypes.c_size_t, _P]),
     "ndq_apply_Q_multi": (_I, [ctypes.POINTER(_QJob), ctypes.c_int32, _P]),
@@ -229,10 +242,29 @@ def set_launch(block: int, xcd_remap: bool = True):
 def autotune(geom: "Geometry", U: "GaugeField", sprec: int, reps: int = 100, rotate_bytes: int = 0, stream=None) -> dict:
     """Time every stencil launch shape for this format and keep the fastest."""
     r = _TuneResult()
-    _check(lib().ndq_autotune(geom.handle, ctypes.byref(U.desc), int(sprec), int(reps), int(rotate_bytes),
+    n = int(lib().ndq_autotune_workspace_bytes(geom.handle, ctypes.byref(U.desc), int(sprec), int(rotate_bytes)))
+    if n == 0:
+        raise NdqError(-1, "bad arguments for ndq_autotune_workspace_bytes")
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    _check(lib().ndq_autotune(geom.handle, ctypes.byref(U.desc), int(sprec), int(reps), int(rotate_bytes), _ptr(ws), n,
                               ctypes.byref(r), _stream(stream)))
+    del ws
     shapes = {f"block{b}_xcd{x}": r.us[2 * i + x] for i, b in enumerate((0, 64, 128, 256)) for x in (0, 1)}
     return {"block": r.block, "xcd_remap": r.xcd_remap, "us_best": r.us_best, "us": shapes, "nsets": r.nsets}
+
+
+def autotune_mrhs(geom: "Geometry", U: "GaugeField", sprec: int, nrhs: int, ny: int = 2, reps: int = 10,
+                  stream=None) -> dict:
+    """Time the work orders of the multi-RHS stencil for this key and keep the fastest
+    (or apply the entry of the NDQ_TUNE_CACHE file)."""
+    n = int(lib().ndq_autotune_mrhs_workspace_bytes(geom.handle, int(sprec), int(nrhs), int(ny)))
+    if n == 0:
+        raise NdqError(-1, "bad arguments for ndq_autotune_mrhs_workspace_bytes")
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    r = _MrhsTuneResult()
+    _check(lib().ndq_autotune_mrhs(geom.handle, ctypes.byref(U.desc), int(sprec), int(nrhs), int(ny), int(reps),
+                                   _ptr(ws), n, ctypes.byref(r), _stream(stream)))
+    return r.as_dict()
 
 
 def get_launch(sprec: int, lprec: int, recon: int) -> dict:

@@ -59,7 +59,7 @@ def test_sizes(ndq):
     assert g.volume == v
     assert g.gauge_bytes(ndq.F64, 18) == v * 4 * 144
     assert g.gauge_bytes(ndq.F32, 12) == v * 4 * 48
-    assert g.gauge_bytes(ndq.F32, 8) == v * 4 * 32
+    assert g.gauge_bytes(ndq.F32, 8) == v * 4 * 32 + 256   # links, then the pack's status word
     assert g.gauge_bytes(ndq.F16, 12) == v * 4 * 24
     assert g.spinor_bytes(ndq.F64, ndq.FULL, 1) == v * 192
     assert g.spinor_bytes(ndq.F32, ndq.EVEN, 12) == 12 * v // 2 * 96

@@ -112,3 +112,46 @@ def test_bad_descriptors(fields):
     with pytest.raises(ndq.NdqError):
         ndq.apply_dslash(f["g"], f["U"], o, o.like())
     still_works(f)
+
+
+def test_autotuners_reject_undersized_workspaces(fields):
+    g, U = fields["g"], fields["U"]
+    from paper_1010_5636_amd.ndq import _TuneResult, _MrhsTuneResult
+    need = int(lib().ndq_autotune_workspace_bytes(g.handle, ctypes.byref(U.desc), ndq.F64, int(1e7)))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    r = _TuneResult()
+    rc = lib().ndq_autotune(g.handle, ctypes.byref(U.desc), ndq.F64, 5, int(1e7), _ptr(ws), need - 1,
+                            ctypes.byref(r), None)
+    assert rc == ENOMEM and b"workspace" in lib().ndq_last_error()
+    need = int(lib().ndq_autotune_mrhs_workspace_bytes(g.handle, ndq.F64, 4, 2))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rm = _MrhsTuneResult()
+    rc = lib().ndq_autotune_mrhs(g.handle, ctypes.byref(U.desc), ndq.F64, 4, 2, 3, _ptr(ws), need - 256,
+                                 ctypes.byref(rm), None)
+    assert rc == ENOMEM
+    still_works(fields)
+
+
+def test_recon8_status_word_in_the_callers_buffer():
+    """8-real links: the singularity flag lives in the field's own status area
+    (ndq_gauge_bytes includes it), cleared on every pack; the unit field is
+    singular, a random field is not, and packing the random field after the
+    unit field succeeds (the flag starts at zero again)."""
+    dims = (4, 4, 4, 4)
+    g = ndq.Geometry(dims)
+    v = geometry.volume(dims)
+    assert g.gauge_bytes(ndq.F32, 8) == v * 4 * 32 + 256
+    cold = cu(synthetic.cold_gauge(dims))
+    hot = cu(synthetic.gauge_field(dims, seed=3))
+    U = ndq.GaugeField(g, ndq.F32, 8)
+    with pytest.raises(ndq.NdqError) as e:
+        lib_rc = lib().ndq_gauge_pack(g.handle, _ptr(cold), ctypes.byref(U.desc), None)
+        ndq.ndq._check(lib_rc)
+    assert e.value.status == -5
+    assert lib().ndq_gauge_pack(g.handle, _ptr(hot), ctypes.byref(U.desc), None) == 0
+    x = ndq.SpinorField.pack(g, cu(synthetic.spinor(v, seed=4)), ndq.F32, ndq.FULL)
+    y = x.like()
+    ndq.apply_Q(g, U, M, x, y)
+    ref = dirac.apply_Q(synthetic.gauge_field(dims, seed=3), synthetic.spinor(v, seed=4), M, dims)
+    got = y.unpack().cpu().numpy()[0]
+    assert np.linalg.norm(got - ref) <= 1e-6 * np.linalg.norm(ref)

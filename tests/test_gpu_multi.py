@@ -125,3 +125,27 @@ def test_multi_max_jobs():
     extra = lattice((4, 4, 4, 4), 1, 70, ndq.F32, ndq.F32, 18)
     with pytest.raises(ndq.NdqError):
         ndq.apply_Q_multi([(L["g"], L["U"], L["m"], L["x"], L["y"]) for L in lats + [extra]])
+
+
+def test_autotune_mrhs_and_cache(tmp_path, monkeypatch):
+    """The work-order autotuner of the multi-RHS stencil picks an order, records
+    it for its key, appends it to the NDQ_TUNE_CACHE file, and a second call
+    takes it from the file without timing; Q stays at its oracle parity."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("NDQ_TUNE_CACHE", str(cache))
+    dims = (8, 8, 8, 16)
+    L = lattice(dims, 6, 61, ndq.F32, ndq.F32, 12)
+    res = ndq.ndq.autotune_mrhs(L["g"], L["U"], ndq.F32, 6, ny=2, reps=5)
+    assert res["cached"] == 0 and res["nshapes"] > 0 and res["us_best"] > 0
+    assert res["us_best"] <= res["us_previous"]
+    got = ndq.ndq.get_mrhs_launch(L["g"], ndq.F32, ndq.F32, 12, 6, 2)
+    assert (got["rg"], got["group_major"], got["chunk"]) == (res["rg"], res["group_major"], res["chunk"])
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("mrhs 8 8 8 16 1 1 12 6 2 ")
+    again = ndq.ndq.autotune_mrhs(L["g"], L["U"], ndq.F32, 6, ny=2, reps=5)
+    assert again["cached"] == 1 and (again["rg"], again["chunk"]) == (res["rg"], res["chunk"])
+    assert len(cache.read_text().strip().splitlines()) == 1
+    ndq.apply_Q(L["g"], L["U"], M, L["x"], L["y"])
+    got = L["y"].unpack().cpu().numpy()
+    for r in range(6):
+        assert rel_l2(got[r], dirac.apply_Q(L["u"], L["psi"][r], M, dims)) <= TOL[ndq.F32]
