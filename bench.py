@@ -198,6 +198,16 @@ def solve_leg(log):
     torch.cuda.synchronize()
     t_fields = time.perf_counter() - t0
     log(f"solve leg: fields {t_fields:.1f} s")
+    # launch shapes of the solver's full-Q launches on this lattice, per format
+    tuned = {}
+    t0 = time.perf_counter()
+    for name, sp, Uf in (("f32-r12", ndq.F32, U32), ("f16-r12", ndq.F16, U16), ("f64-r18", ndq.F64, U64)):
+        r = ndq.autotune(g, Uf, sp, reps=20, rotate_bytes=int(6e8), full_q=True)
+        tuned[name] = {"block": r["block"], "xcd_remap": r["xcd_remap"], "us_best": round(r["us_best"], 2)}
+    for name, sp, Uf in (("f32-r12", ndq.F32, U32), ("f16-r12", ndq.F16, U16)):
+        r = ndq.ndq.autotune_mrhs(g, Uf, sp, 12, ny=2, reps=5)
+        tuned[name + "_12rhs"] = {k: r[k] for k in ("rg", "group_major", "chunk", "us_best", "us_previous")}
+    log(f"solve leg: launch tuning {time.perf_counter() - t0:.1f} s: {tuned}")
     t0 = time.perf_counter()
     # a block of 20 + 40 vectors: the 20 lowest modes sit in a dense cluster, and
     # the larger block converges in fewer filter steps (measured 36 s vs 55 s with 20 + 8)
@@ -221,6 +231,7 @@ def solve_leg(log):
                         "lam_next": info["lam_next"], "max_rho": info["max_rho"], "kappa_plus": info["kappa_plus"],
                         "kappa_minus": info["kappa_minus"], "q_applies": info["q_applies"],
                         "restarts": info["restarts"], "cheb_degree": info["cheb_degree"], "block": SOLVE_NEV + 40},
+           "launch_tuning": tuned,
            "approximant": {"kind": "minimax polynomial (Clenshaw)", "eps": eps, "degree_fp64": ap64.n,
                            "delta_fp64": ap64.delta, "degree_inner": ap_lo.n, "delta_inner": ap_lo.delta}}
     runs = {}
@@ -375,6 +386,17 @@ def copy_reference(nbytes, reps=400):
             "frac": round(2 * half / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def launch_floor(reps=1000):
+    """Back-to-back launches of the smallest kernel (a one-element fill) timed as
+    the headline is: the per-launch floor that any kernel pays in such a chain."""
+    import torch
+    t = torch.empty(1, dtype=torch.float32, device="cuda")
+    f = lambda: t.fill_(1.0)  # noqa: E731
+    for _ in range(20):
+        f()
+    return {"us": round(_time_events(f, reps) * 1e3, 3), "kernel": "one-element fill, back to back"}
+
+
 BATCH_DIMS = (64, 32, 32, 32)
 MULTI_DIMS = [(8, 8, 8, 8), (12, 12, 12, 12), (32, 16, 16, 16)]
 
@@ -398,7 +420,35 @@ def batch_leg(log):
     v = g.volume
     u = torch.from_numpy(synthetic.gauge_field(BATCH_DIMS)).to(dev)
     U = ndq.GaugeField.pack(g, u, ndq.F32, 18)
+    # the even/odd dslash on the same 32^3x64 links in the headline format (F32
+    # spinors, 12-real F32 links): 403 MB of links and 2 x 101 MB of spinors per
+    # apply, beyond the 256 MB Infinity Cache, so every apply streams from HBM
+    U12 = ndq.GaugeField.pack(g, u, ndq.F32, 12)
     del u
+    e = ndq.SpinorField.pack(g, torch.from_numpy(synthetic.spinor(v // 2)).to(dev), ndq.F32, ndq.EVEN)
+    o = e.like(parity=ndq.ODD)
+    tune = ndq.autotune(g, U12, ndq.F32, reps=50)
+    par = {"k": 0}
+
+    def dslash_big():
+        if par["k"] % 2 == 0:
+            ndq.apply_dslash(g, U12, e, o)
+        else:
+            ndq.apply_dslash(g, U12, o, e)
+        par["k"] += 1
+
+    for _ in range(10):
+        dslash_big()
+    ms_d = _time_events(dslash_big, 200)
+    alg_d = 576 * (v // 2)
+    out["dslash_32c64"] = {
+        "workload": "even/odd dslash, 32^3x64, F32 spinors, 12-real F32 links, random SU(3) links (width 0.3)",
+        "us": round(ms_d * 1e3, 3), "alg_bytes": alg_d, "gbs": round(alg_d / (ms_d * 1e-3) / 1e9, 1),
+        "frac_hbm": round(alg_d / (ms_d * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "gflops": round(FLOP_PER_SITE * (v // 2) / (ms_d * 1e-3) / 1e9, 1),
+        "launch": {"block": tune["block"], "xcd_remap": tune["xcd_remap"]}}
+    log(f"batch leg: dslash 32^3x64 {ms_d * 1e3:.2f} us ({out['dslash_32c64']['frac_hbm']:.3f} of HBM peak)")
+    del e, o, U12
     canon = torch.zeros((12, v, 4, 3), dtype=torch.complex128, device=dev)
     for s in range(4):
         for c in range(3):
@@ -411,6 +461,8 @@ def batch_leg(log):
     ys = [ndq.SpinorField(g, ndq.F32, ndq.FULL, 1, buffer=y.buf[r * rb:(r + 1) * rb]) for r in range(12)]
     torch.cuda.synchronize()
     log(f"batch leg: 32^3x64 fields {time.perf_counter() - t0:.1f} s")
+
+    tuned = ndq.ndq.autotune_mrhs(g, U, ndq.F32, 12, ny=2, reps=5)
 
     def batched():
         ndq.apply_Q(g, U, M, x, y)
@@ -432,6 +484,7 @@ def batch_leg(log):
         "batched_frac_hbm": round(alg_b / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "single_hbm_gbs": round(12 * 480 * v / (ms_s * 1e-3) / 1e9, 1)}
     out["point_sources_32c64"]["work_order"] = ndq.ndq.get_mrhs_launch(g, ndq.F32, ndq.F32, 18, 12, 2)
+    out["point_sources_32c64"]["autotune_mrhs"] = {k: tuned[k] for k in ("nshapes", "us_best", "us_previous")}
     log(f"batch leg: 12 point sources batched {ms_b:.3f} ms vs single {ms_s:.3f} ms")
     del x, y, xs, ys, U
     torch.cuda.empty_cache()
@@ -678,7 +731,7 @@ def main():
             tune = None
         else:
             tune = ndq.autotune(g, sets[0][0], sp, reps=200, rotate_bytes=int(ROTATE_BYTES))
-        launch = ndq.ndq.get_launch(sp, lp, recon)
+        launch = ndq.ndq.get_launch_lattice(g, sp, lp, recon, 1)
 
         def step(k):
             U, e, o = sets[k % nsets]
@@ -827,7 +880,8 @@ def main():
                      "frac": round(hr["frac_hbm"], 4), "traffic": traffic,
                      "kernel": kernel_name(hr["launch"]), "alg_bytes_per_launch": hr["alg_bytes_per_launch"],
                      "kernel_us_avg": round(hr["kernel_us_avg"], 3),
-                     "copy_same_bytes": copy_reference(hr["alg_bytes_per_launch"])},
+                     "copy_same_bytes": copy_reference(hr["alg_bytes_per_launch"]),
+                     "launch_floor": launch_floor()},
         "variants": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in r.items()}
                      for k, r in results.items()},
     }

@@ -486,12 +486,17 @@ int ndq_get_launch_for(int sprec, int lprec, int recon, int* block, int* xcd_rem
  * (block 0/64/128/256, XCD remap off/on), on ceil(rotate_bytes / set size)
  * rotating copies of (links, even spinor, odd spinor) so that consecutive
  * applies stream from HBM as in a solver (rotate_bytes <= 0: one set), and
- * records the fastest shape for that storage format as ndq_set_launch_for
- * does; the shape already in use is kept if it is within 3% of the fastest.
- * The copies live in the caller's workspace ws of at least
+ * records the fastest shape for dslash launches of that storage format on
+ * this lattice (other lattices keep the format's shape of ndq_set_launch_for,
+ * and a later ndq_set_launch_for of the format replaces the tuned shapes);
+ * the shape already in use is kept if it is within 3% of the fastest.  The
+ * copies live in the caller's workspace ws of at least
  * ndq_autotune_workspace_bytes(g, U, sprec, rotate_bytes) bytes (the first set
- * uses U itself).  Synchronises `stream`.
- * Errors: NDQ_EINVAL, NDQ_EPREC, NDQ_ENOMEM, NDQ_EHIP (the previous shape is kept). */
+ * uses U itself).  ndq_autotune_q does the same for the full Q launches (both
+ * output parities in one launch, as in ndq_apply_Q and the sign iterations)
+ * with full-field sets (ndq_autotune_q_workspace_bytes).  Synchronises
+ * `stream`.  Errors: NDQ_EINVAL, NDQ_EPREC, NDQ_ENOMEM, NDQ_EHIP (the previous
+ * shape is kept). */
 typedef struct {
     int32_t block;        /* chosen shape                                            */
     int32_t xcd_remap;
@@ -502,6 +507,14 @@ typedef struct {
 size_t ndq_autotune_workspace_bytes(const ndq_geom* g, const ndq_gauge* U, int sprec, int64_t rotate_bytes);
 int ndq_autotune(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, int64_t rotate_bytes, void* ws,
                  size_t ws_bytes, ndq_tune_result* out, void* stream);
+size_t ndq_autotune_q_workspace_bytes(const ndq_geom* g, const ndq_gauge* U, int sprec, int64_t rotate_bytes);
+int ndq_autotune_q(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, int64_t rotate_bytes, void* ws,
+                   size_t ws_bytes, ndq_tune_result* out, void* stream);
+
+/* The launch shape used on lattice g for one storage format and launch kind
+ * (ny = 1: dslash, 2: Q): the autotuner's choice for this lattice, else the
+ * format's (host outputs). */
+int ndq_get_launch_lattice(const ndq_geom* g, int sprec, int lprec, int recon, int ny, int* block, int* xcd_remap);
 
 /* Autotuner of the multi-right-hand-side work order (see ndq_set_mrhs_launch)
  * for lattice g, links U, spinor precision sprec, nrhs >= 2 fields and ny

@@ -403,19 +403,27 @@ __global__ void k_mode_coef(const double* c, const double* d, ModeSigns sg, int 
 // Basis rotation dst_j = sum_i src_i Y[i][j] for the FP64 full spinors of a
 // contiguous block (Y complex, row-major nsrc x k, on the device).  One lane
 // per (complex component c, site s), sites fastest so that every load is a
-// contiguous run of one plane; grid row y computes the outputs
-// j = kRotJ y .. kRotJ y + kRotJ - 1, so each source plane is read ceil(k / kRotJ)
-// times (the coefficients are uniform across the grid row).  The sum over i
-// runs in index order for every output, as a plain loop would.
+// contiguous run of one plane; the outputs come in groups of kRotJ, and the
+// groups of one run of lanes are the wavefronts of one workgroup (rot_shape),
+// so the source planes they all read leave HBM once.  The sum over i runs in
+// index order for every output, as a plain loop would.
 constexpr int kRotJ = 16;
-__global__ void __launch_bounds__(kBlock) k_rotate(const char* __restrict__ src, int nsrc, const double* __restrict__ Y,
-                                                   int k, char* __restrict__ dst, int64_t vbytes, SpinorView lay,
-                                                   int32_t n) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+
+// Workgroup shape for ngroups output groups: wpg wavefronts of distinct lanes
+// per group (4 wavefronts in all for 1, 2 or 4 groups).
+__host__ __device__ inline int rot_wpg(int ngroups) { return ngroups == 1 ? 4 : ngroups == 2 ? 2 : 1; }
+
+__global__ void __launch_bounds__(256) k_rotate(const char* __restrict__ src, int nsrc, const double* __restrict__ Y,
+                                                int k, char* __restrict__ dst, int64_t vbytes, SpinorView lay,
+                                                int32_t n) {
+    const int ng = (k + kRotJ - 1) / kRotJ;
+    const int wpg = rot_wpg(ng);
+    const int wave = threadIdx.x >> 6;
+    const int64_t t = ((int64_t)blockIdx.x * wpg + wave % wpg) * 64 + (threadIdx.x & 63);
     if (t >= 12 * (int64_t)n) return;
     const int c = (int)(t / n);
     const int32_t s = (int32_t)(t - (int64_t)c * n);
-    const int j0 = kRotJ * blockIdx.y;
+    const int j0 = kRotJ * (wave / wpg);
     const int cnt = min(kRotJ, k - j0);
     C<double> acc[kRotJ];
 #pragma unroll
@@ -493,14 +501,17 @@ __device__ __forceinline__ double2 field_comp(const char* base, int32_t V, int c
 }
 
 // B may be F64, F32 or F16 (PB; converted to FP64 on load); A is FP64.
+// A workgroup takes one chunk of sites with one wavefront per 16-row tile of
+// G, so the B fields of the chunk are loaded by all its wavefronts at about the
+// same time and leave HBM once.
 template <int PB>
 __global__ void __launch_bounds__(256) k_gram(const char* __restrict__ A, int na, const char* __restrict__ B, int nb,
-                                              int64_t vb, int64_t vbB, int32_t V, int32_t sites_per_wave, int nwaves,
+                                              int64_t vb, int64_t vbB, int32_t V, int32_t sites_per_wave, int nchunks,
                                               double* __restrict__ partials) {
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wave >= nwaves) return;   // whole wavefronts only
-    const int ti = blockIdx.y;
+    const int wave = blockIdx.x;   // the chunk
+    if (wave >= nchunks) return;
+    const int ti = threadIdx.x >> 6;
     const int t = lane & 15, kk = lane >> 4;
     const int ntj = (nb + 15) / 16;
     const int NI = 16 * ((na + 15) / 16), NJ = 16 * ntj;
@@ -517,6 +528,9 @@ __global__ void __launch_bounds__(256) k_gram(const char* __restrict__ A, int na
     }
     for (int c = 0; c < 12; ++c) {
         const int64_t plane = (int64_t)c * V;
+        // several steps' loads in flight at once (each step only adds into
+        // the accumulators)
+#pragma unroll 4
         for (int32_t s = s0; s < s1; s += 4) {
             const int32_t site = s + kk;
             const bool vs = site < s1;
@@ -550,22 +564,28 @@ __global__ void __launch_bounds__(256) k_gram(const char* __restrict__ A, int na
     }
 }
 
-// G[i][j] = sum over wavefronts w (in order) of the partial tiles.
+// G[i][j] = sum over the chunks (in a fixed order) of the partial tiles, one
+// workgroup per element.
 __global__ void __launch_bounds__(kBlock) k_gram_reduce(const double* __restrict__ partials, int na, int nb,
-                                                        int nwaves, double* __restrict__ G) {
-    const int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e >= na * nb) return;
+                                                        int nchunks, double* __restrict__ G) {
+    __shared__ double lds[kBlock / 64];
+    const int e = blockIdx.x;
     const int i = e / nb, j = e - (e / nb) * nb;
     const int NI = 16 * ((na + 15) / 16), NJ = 16 * ((nb + 15) / 16);
     const double2* p = reinterpret_cast<const double2*>(partials);
     double sr = 0.0, si = 0.0;
-    for (int w = 0; w < nwaves; ++w) {
+    for (int w = threadIdx.x; w < nchunks; w += kBlock) {
         const double2 v = p[((int64_t)w * NI + i) * NJ + j];
         sr += v.x;
         si += v.y;
     }
-    G[2 * e] = sr;
-    G[2 * e + 1] = si;
+    sr = block_sum(sr, lds);
+    __syncthreads();
+    si = block_sum(si, lds);
+    if (threadIdx.x == 0) {
+        G[2 * e] = sr;
+        G[2 * e + 1] = si;
+    }
 }
 
 // Projection coefficients of a block of R fields: coef[k][r] = sc * (use_sign ?
@@ -582,21 +602,36 @@ __global__ void k_mode_coef_block(const double* c, const double* d, ModeSigns sg
 
 // out_r = in_r + sum_k coef[k][r] u_k for a block of fields (r < nr), one lane
 // per (complex component c, site s) with sites fastest, so that every load is
-// a contiguous run of one plane; grid row y takes the fields r = kRotJ y ..
-// kRotJ y + kRotJ - 1, which read each mode plane once between them.  The sum
-// runs in the order of k_mode_update (start from in, add the modes in index
-// order, FP64).  PI: precision of `in` (F64, F32 or F16); PO: precision of
-// `out` (F64 or F32; an F16 result goes through an F32 block and k_convert,
-// which rounds exactly as k_mode_update<P16> does).
+// a contiguous run of one plane; for F32 output the two components of one
+// 16-byte word sit in adjacent lanes (lane pair = site, lane parity =
+// component), so each word is written whole by one store instruction.  The
+// fields come in groups of kRotJ laid out over the wavefronts of a workgroup as
+// in k_rotate, so the mode planes leave HBM once.  The sum runs in the order
+// of k_mode_update (start from in, add the modes in index order, FP64).  PI:
+// precision of `in` (F64, F32 or F16); PO: precision of `out` (F64 or F32; an
+// F16 result goes through an F32 block and k_convert, which rounds exactly as
+// k_mode_update<P16> does).
 template <int PI, int PO>
-__global__ void __launch_bounds__(kBlock) k_mode_update_block(const char* __restrict__ modes, int64_t mode_bytes,
-                                                              int nev, const double* __restrict__ coef, int nr,
-                                                              SpinorView in, SpinorView out, int32_t n) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__global__ void __launch_bounds__(256) k_mode_update_block(const char* __restrict__ modes, int64_t mode_bytes,
+                                                           int nev, const double* __restrict__ coef, int nr,
+                                                           SpinorView in, SpinorView out, int32_t n) {
+    const int ng = (nr + kRotJ - 1) / kRotJ;
+    const int wpg = rot_wpg(ng);
+    const int wave = threadIdx.x >> 6;
+    const int64_t t = ((int64_t)blockIdx.x * wpg + wave % wpg) * 64 + (threadIdx.x & 63);
     if (t >= 12 * (int64_t)n) return;
-    const int c = (int)(t / n);
-    const int32_t s = (int32_t)(t - (int64_t)c * n);
-    const int r0 = kRotJ * blockIdx.y;
+    int c;
+    int32_t s;
+    if constexpr (PO == P32) {
+        const int64_t pr = t >> 1;   // (plane j, site s) pair
+        const int j = (int)(pr / n);
+        s = (int32_t)(pr - (int64_t)j * n);
+        c = 2 * j + (int)(t & 1);
+    } else {
+        c = (int)(t / n);
+        s = (int32_t)(t - (int64_t)c * n);
+    }
+    const int r0 = kRotJ * (wave / wpg);
     const int cnt = min(kRotJ, nr - r0);
     C<double> acc[kRotJ];
 #pragma unroll
@@ -745,30 +780,33 @@ int convert(const ndq_geom* g, const ndq_spinor* dst, const ndq_spinor* src, hip
 }
 
 namespace {
-constexpr int kGramWaves = 1024;
-int gram_waves(const ndq_geom* g) {
-    return (int)std::max<int64_t>(1, std::min<int64_t>(kGramWaves, (g->volume + 63) / 64));
+// Site chunks of the Gram kernel: enough workgroups to fill the device, at
+// least 64 sites each, and at most 32 MiB of partial tiles.
+int gram_chunks(const ndq_geom* g, int na, int nb) {
+    const int64_t tile = (int64_t)16 * ((na + 15) / 16) * 16 * ((nb + 15) / 16) * 2 * sizeof(double);
+    const int64_t cap = std::max<int64_t>(1, (int64_t(32) << 20) / tile);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(4096, cap), (g->volume + 63) / 64));
 }
 }  // namespace
 
 size_t gram_partials_bytes(const ndq_geom* g, int na, int nb) {
     const int NI = 16 * ((na + 15) / 16), NJ = 16 * ((nb + 15) / 16);
-    return (size_t)gram_waves(g) * NI * NJ * 2 * sizeof(double);
+    return (size_t)gram_chunks(g, na, nb) * NI * NJ * 2 * sizeof(double);
 }
 
 int gram(const ndq_geom* g, const void* A, int na, const void* B, int nb, double* partials, double* G,
          hipStream_t st) {
     if (na < 1 || nb < 1 || na > 64 || nb > 64) return fail(NDQ_EINVAL, "gram: block sizes must be in [1, 64]");
-    const int nw = gram_waves(g);
+    const int nw = gram_chunks(g, na, nb);
     const int64_t V = g->volume;
     int32_t spw = (int32_t)((V + nw - 1) / nw);
     spw = (spw + 3) & ~3;
     const int64_t vb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
-    const dim3 grid((unsigned)((nw + 3) / 4), (unsigned)((na + 15) / 16));
-    hipLaunchKernelGGL(k_gram<P64>, grid, dim3(256), 0, st, static_cast<const char*>(A), na, static_cast<const char*>(B),
+    const dim3 block(64 * ((na + 15) / 16));
+    hipLaunchKernelGGL(k_gram<P64>, dim3(nw), block, 0, st, static_cast<const char*>(A), na, static_cast<const char*>(B),
                        nb, vb, vb, (int32_t)V, spw, nw, partials);
     NDQ_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks((int64_t)na * nb)), dim3(kBlock), 0, st, partials, na, nb, nw, G);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(na * nb), dim3(kBlock), 0, st, partials, na, nb, nw, G);
     NDQ_HIP(hipGetLastError());
     return NDQ_OK;
 }
@@ -821,22 +859,22 @@ int gram_block(const ndq_geom* g, const void* A, int na, const ndq_spinor* B, do
                hipStream_t st) {
     const int nb = B->nrhs;
     if (na < 1 || nb < 1 || na > 64 || nb > 64) return fail(NDQ_EINVAL, "gram: block sizes must be in [1, 64]");
-    const int nw = gram_waves(g);
+    const int nw = gram_chunks(g, na, nb);
     const int64_t V = g->volume;
     int32_t spw = (int32_t)((V + nw - 1) / nw);
     spw = (spw + 3) & ~3;
     const int64_t vb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
     const int64_t vbB = spinor_rhs_bytes(g, B->prec, NDQ_FULL);
-    const dim3 grid((unsigned)((nw + 3) / 4), (unsigned)((na + 15) / 16));
+    const dim3 grid(nw), blk(64 * ((na + 15) / 16));
     const char* a = static_cast<const char*>(A);
     const char* b = static_cast<const char*>(B->data);
     switch (B->prec) {
-        case NDQ_F64: hipLaunchKernelGGL(k_gram<P64>, grid, dim3(256), 0, st, a, na, b, nb, vb, vbB, (int32_t)V, spw, nw, partials); break;
-        case NDQ_F32: hipLaunchKernelGGL(k_gram<P32>, grid, dim3(256), 0, st, a, na, b, nb, vb, vbB, (int32_t)V, spw, nw, partials); break;
-        default: hipLaunchKernelGGL(k_gram<P16>, grid, dim3(256), 0, st, a, na, b, nb, vb, vbB, (int32_t)V, spw, nw, partials); break;
+        case NDQ_F64: hipLaunchKernelGGL(k_gram<P64>, grid, blk, 0, st, a, na, b, nb, vb, vbB, (int32_t)V, spw, nw, partials); break;
+        case NDQ_F32: hipLaunchKernelGGL(k_gram<P32>, grid, blk, 0, st, a, na, b, nb, vb, vbB, (int32_t)V, spw, nw, partials); break;
+        default: hipLaunchKernelGGL(k_gram<P16>, grid, blk, 0, st, a, na, b, nb, vb, vbB, (int32_t)V, spw, nw, partials); break;
     }
     NDQ_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks((int64_t)na * nb)), dim3(kBlock), 0, st, partials, na, nb, nw, G);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(na * nb), dim3(kBlock), 0, st, partials, na, nb, nw, G);
     NDQ_HIP(hipGetLastError());
     return NDQ_OK;
 }
@@ -857,14 +895,18 @@ int mode_update_block(const ndq_geom* g, const void* modes, int nev, const doubl
     const SpinorView iv = flat_view(g, in), ov = flat_view(g, out);
     const int64_t mb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
     const char* mp = static_cast<const char*>(modes);
+    const int ng = (nr + kRotJ - 1) / kRotJ;
+    const int wpg = rot_wpg(ng);
     const int64_t lanes = 12 * (int64_t)g->volume;
-    const dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock), (unsigned)((nr + kRotJ - 1) / kRotJ));
+    const dim3 grid((unsigned)((lanes + 64 * wpg - 1) / (64 * wpg)));
+    const dim3 blk(64 * wpg * ng);
     const int32_t n = (int32_t)g->volume;
+    if (ng * wpg > 4) return fail(NDQ_EINVAL, "mode update: at most 64 fields per block");
     const int key = in->prec * 3 + out->prec;
     switch (key) {
-        case NDQ_F64 * 3 + NDQ_F64: hipLaunchKernelGGL((k_mode_update_block<P64, P64>), grid, dim3(kBlock), 0, st, mp, mb, nev, coef, nr, iv, ov, n); break;
-        case NDQ_F32 * 3 + NDQ_F32: hipLaunchKernelGGL((k_mode_update_block<P32, P32>), grid, dim3(kBlock), 0, st, mp, mb, nev, coef, nr, iv, ov, n); break;
-        case NDQ_F16 * 3 + NDQ_F32: hipLaunchKernelGGL((k_mode_update_block<P16, P32>), grid, dim3(kBlock), 0, st, mp, mb, nev, coef, nr, iv, ov, n); break;
+        case NDQ_F64 * 3 + NDQ_F64: hipLaunchKernelGGL((k_mode_update_block<P64, P64>), grid, blk, 0, st, mp, mb, nev, coef, nr, iv, ov, n); break;
+        case NDQ_F32 * 3 + NDQ_F32: hipLaunchKernelGGL((k_mode_update_block<P32, P32>), grid, blk, 0, st, mp, mb, nev, coef, nr, iv, ov, n); break;
+        case NDQ_F16 * 3 + NDQ_F32: hipLaunchKernelGGL((k_mode_update_block<P16, P32>), grid, blk, 0, st, mp, mb, nev, coef, nr, iv, ov, n); break;
         default: return fail(NDQ_EPREC, "mode update: unsupported precision pair (%d -> %d)", in->prec, out->prec);
     }
     NDQ_HIP(hipGetLastError());
@@ -882,9 +924,12 @@ int rotate(const ndq_geom* g, const void* src, int nsrc, const double* Y, int k,
     ndq_spinor d = {const_cast<void*>(src), NDQ_F64, NDQ_FULL, 1};
     const SpinorView lay = flat_view(g, &d);
     const int64_t vb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
+    const int ng = (k + kRotJ - 1) / kRotJ;
+    if (ng > 4) return fail(NDQ_EINVAL, "rotate: at most 64 outputs");
+    const int wpg = rot_wpg(ng);
     const int64_t lanes = 12 * (int64_t)g->volume;
-    const dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock), (k + kRotJ - 1) / kRotJ);
-    hipLaunchKernelGGL(k_rotate, grid, dim3(kBlock), 0, st, static_cast<const char*>(src), nsrc, Y, k,
+    const dim3 grid((unsigned)((lanes + 64 * wpg - 1) / (64 * wpg)));
+    hipLaunchKernelGGL(k_rotate, grid, dim3(64 * wpg * ng), 0, st, static_cast<const char*>(src), nsrc, Y, k,
                        static_cast<char*>(dst), vb, lay, (int32_t)g->volume);
     NDQ_HIP(hipGetLastError());
     return NDQ_OK;

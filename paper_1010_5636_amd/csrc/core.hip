@@ -197,6 +197,36 @@ MrhsKey mrhs_key(const GeomK& g, int sprec, int lprec, int recon, int nrhs, int 
 
 Tuning& tuning(int sprec, int lprec, int recon) { return g_tuning[sprec][lprec][recon_index(recon)]; }
 
+namespace {
+using LaunchKey = std::tuple<int, int, int, int, int, int, int, int>;
+std::mutex g_launch_mu;
+std::map<LaunchKey, Tuning> g_launch;
+LaunchKey launch_key(const GeomK& g, int sprec, int lprec, int recon, int ny) {
+    return LaunchKey{g.n0, g.n1, g.n2, g.n3, sprec, lprec, recon, ny};
+}
+}  // namespace
+
+Tuning launch_tuning(const GeomK& g, int sprec, int lprec, int recon, int ny) {
+    std::lock_guard<std::mutex> lock(g_launch_mu);
+    const auto it = g_launch.find(launch_key(g, sprec, lprec, recon, ny));
+    if (it != g_launch.end()) return it->second;
+    return tuning(sprec, lprec, recon);
+}
+
+void set_launch_tuning(const GeomK& g, int sprec, int lprec, int recon, int ny, const Tuning& t) {
+    std::lock_guard<std::mutex> lock(g_launch_mu);
+    g_launch[launch_key(g, sprec, lprec, recon, ny)] = t;
+}
+
+void clear_launch_tuning(int sprec, int lprec, int recon) {
+    std::lock_guard<std::mutex> lock(g_launch_mu);
+    for (auto it = g_launch.begin(); it != g_launch.end();) {
+        const LaunchKey& k = it->first;
+        if (std::get<4>(k) == sprec && std::get<5>(k) == lprec && std::get<6>(k) == recon) it = g_launch.erase(it);
+        else ++it;
+    }
+}
+
 // Defaults from a sweep of the work order on 24^3x48 and 32^3x64 (12 and 60
 // fields): blocks of 8 or more F32/F64 fields run in group-major order with 6
 // fields per workgroup, and the tiles in chunks spanning two x1 rows of the
@@ -279,6 +309,7 @@ extern "C" int ndq_set_launch_for(int sprec, int lprec, int recon, int block, in
     ndq::Tuning& t = ndq::tuning(sprec, lprec, recon);
     t.block = block;
     t.xcd_remap = xcd_remap ? 1 : 0;
+    ndq::clear_launch_tuning(sprec, lprec, recon);   // an explicit shape replaces tuned ones
     return NDQ_OK;
 }
 
@@ -298,5 +329,16 @@ extern "C" int ndq_set_launch(int block, int xcd_remap) {
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
             for (int r : {18, 12, 8}) ndq_set_launch_for(a, b, r, block, xcd_remap);
+    return NDQ_OK;
+}
+
+extern "C" int ndq_get_launch_lattice(const ndq_geom* g, int sprec, int lprec, int recon, int ny, int* block,
+                                      int* xcd_remap) {
+    if (!g || sprec < NDQ_F64 || sprec > NDQ_F16 || lprec < NDQ_F64 || lprec > NDQ_F16 ||
+        (recon != 18 && recon != 12 && recon != 8) || (ny != 1 && ny != 2) || !block || !xcd_remap)
+        return ndq::fail(NDQ_EINVAL, "ndq_get_launch_lattice: bad argument");
+    const ndq::Tuning t = ndq::launch_tuning(g->k, sprec, lprec, recon, ny);
+    *block = t.block;
+    *xcd_remap = t.xcd_remap;
     return NDQ_OK;
 }

@@ -43,7 +43,7 @@ int q_combo_block(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spi
 }
 
 int q_blocks(const ndq_geom* g, const ndq_gauge* U, int sprec) {
-    return wilson_blocks(g, tuning(sprec, U->prec, U->recon).block, 2);
+    return wilson_blocks(g, launch_tuning(g->k, sprec, U->prec, U->recon, 2).block, 2);
 }
 
 int q_combo(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* in, const ndq_spinor* out, Coef c0,
@@ -64,8 +64,7 @@ int q_combo(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spinor* i
     a.nv = nv;
     for (int j = 0; j < nv; ++j) a.cv[j] = cv[j];
     a.partials = partials;
-    const Tuning& t = tuning(in->prec, U->prec, U->recon);
-    NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 2, t.block, st));
+    NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 2, -1, st));
     return NDQ_OK;
 }
 
@@ -238,7 +237,7 @@ int rational_apply(const ndq_geom* g, const ndq_gauge* U, double m, const Approx
             const void* ws;
         } head;
         memset(&head, 0, sizeof(head));
-        const Tuning& tu = tuning(prec, U->prec, U->recon);
+        const Tuning tu = launch_tuning(g->k, prec, U->prec, U->recon, 2);
         head.g = g;
         for (int d = 0; d < 4; ++d) head.dims[d] = g->dims[d];
         head.links = U->data;

@@ -1,9 +1,10 @@
 // Launch autotuners of the stencil.
 //
-// ndq_autotune: the even/odd dslash of one storage format on one lattice for
-// every launch shape (one lane per site with 64/128/256-lane workgroups, or the
-// direction split) with and without the XCD remap; records the fastest for
-// that format (ndq_set_launch_for).
+// ndq_autotune / ndq_autotune_q: the even/odd dslash (or the full Q) of one
+// storage format on one lattice for every launch shape (one lane per site with
+// 64/128/256-lane workgroups, or the direction split) with and without the XCD
+// remap; records the fastest for that lattice, format and launch kind (other
+// lattices keep the format's shape).
 //
 // ndq_autotune_mrhs: the work order of the multi-right-hand-side stencil
 // (fields per workgroup, group order, tile chunk) for one lattice, format,
@@ -32,15 +33,21 @@ const int kBlocks[4] = {0, 64, 128, 256};
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-int dslash_sets(const ndq_geom* g, const ndq_gauge* U, int sprec, int64_t rotate_bytes) {
-    const size_t set_bytes = ndq_gauge_bytes(g, U->prec, U->recon) + 2 * (size_t)spinor_rhs_bytes(g, sprec, NDQ_EVEN);
+// One rotating set: links and the input and output spinors of a dslash (ny =
+// 1: two half fields) or of Q (ny = 2: two full fields).
+size_t set_spinor_bytes(const ndq_geom* g, int sprec, int ny) {
+    return (size_t)spinor_rhs_bytes(g, sprec, ny == 2 ? NDQ_FULL : NDQ_EVEN);
+}
+
+int dslash_sets(const ndq_geom* g, const ndq_gauge* U, int sprec, int64_t rotate_bytes, int ny) {
+    const size_t set_bytes = ndq_gauge_bytes(g, U->prec, U->recon) + 2 * set_spinor_bytes(g, sprec, ny);
     int nsets = rotate_bytes > 0 ? (int)((rotate_bytes + (int64_t)set_bytes - 1) / (int64_t)set_bytes) : 1;
     return std::max(1, std::min(nsets, 256));
 }
 
-size_t dslash_ws(const ndq_geom* g, const ndq_gauge* U, int sprec, int nsets) {
+size_t dslash_ws(const ndq_geom* g, const ndq_gauge* U, int sprec, int nsets, int ny) {
     const size_t lb = align256(ndq_gauge_bytes(g, U->prec, U->recon));
-    const size_t sb = align256((size_t)spinor_rhs_bytes(g, sprec, NDQ_EVEN));
+    const size_t sb = align256(set_spinor_bytes(g, sprec, ny));
     return (size_t)(nsets - 1) * lb + (size_t)nsets * 2 * sb + 256;
 }
 
@@ -128,25 +135,23 @@ int check_format(const ndq_gauge* U, int sprec, const char* who) {
 
 }  // namespace
 
-extern "C" size_t ndq_autotune_workspace_bytes(const ndq_geom* g, const ndq_gauge* U, int sprec, int64_t rotate_bytes) {
-    if (!g || !U || check_gauge(U) || sprec < NDQ_F64 || sprec > NDQ_F16) return 0;
-    return dslash_ws(g, U, sprec, dslash_sets(g, U, sprec, rotate_bytes));
-}
+namespace {
 
-extern "C" int ndq_autotune(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, int64_t rotate_bytes, void* ws,
-                            size_t ws_bytes, ndq_tune_result* out, void* stream) {
-    if (!g || !out) return fail(NDQ_EINVAL, "ndq_autotune: NULL argument");
-    int rc = check_format(U, sprec, "ndq_autotune");
+int autotune_single(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, int64_t rotate_bytes, void* ws,
+                    size_t ws_bytes, ndq_tune_result* out, void* stream, int ny) {
+    const char* who = ny == 2 ? "ndq_autotune_q" : "ndq_autotune";
+    if (!g || !out) return fail(NDQ_EINVAL, "%s: NULL argument", who);
+    int rc = check_format(U, sprec, who);
     if (rc) return rc;
-    if (reps < 1) return fail(NDQ_EINVAL, "ndq_autotune: reps must be >= 1");
+    if (reps < 1) return fail(NDQ_EINVAL, "%s: reps must be >= 1", who);
     hipStream_t st = as_stream(stream);
-    const int nsets = dslash_sets(g, U, sprec, rotate_bytes);
-    const size_t need = dslash_ws(g, U, sprec, nsets);
-    if (!ws || ws_bytes < need) return fail(NDQ_ENOMEM, "ndq_autotune: workspace too small (need %zu bytes)", need);
+    const int nsets = dslash_sets(g, U, sprec, rotate_bytes, ny);
+    const size_t need = dslash_ws(g, U, sprec, nsets, ny);
+    if (!ws || ws_bytes < need) return fail(NDQ_ENOMEM, "%s: workspace too small (need %zu bytes)", who, need);
     const size_t lb = align256(ndq_gauge_bytes(g, U->prec, U->recon));
-    const size_t sb = align256((size_t)spinor_rhs_bytes(g, sprec, NDQ_EVEN));
-    // set k: links (set 0 uses the caller's), even and odd spinors
-    std::vector<void*> links(nsets), even(nsets), odd(nsets);
+    const size_t sb = align256(set_spinor_bytes(g, sprec, ny));
+    // set k: links (set 0 uses the caller's), two spinor fields
+    std::vector<void*> links(nsets), fa(nsets), fb(nsets);
     char* p = static_cast<char*>(ws);
     for (int k = 0; k < nsets; ++k) {
         if (k == 0) {
@@ -156,38 +161,44 @@ extern "C" int ndq_autotune(const ndq_geom* g, const ndq_gauge* U, int sprec, in
             p += lb;
             NDQ_HIP(hipMemcpyAsync(links[k], U->data, ndq_gauge_bytes(g, U->prec, U->recon), hipMemcpyDeviceToDevice, st));
         }
-        even[k] = p;
+        fa[k] = p;
         p += sb;
-        odd[k] = p;
+        fb[k] = p;
         p += sb;
         // any finite pattern: 0x3c00 halves (1.0 in F16), a small number in F32/F64
-        NDQ_HIP(hipMemsetD32Async(even[k], 0x3c003c00u, sb / 4, st));
-        NDQ_HIP(hipMemsetD32Async(odd[k], 0x3c003c00u, sb / 4, st));
+        NDQ_HIP(hipMemsetD32Async(fa[k], 0x3c003c00u, sb / 4, st));
+        NDQ_HIP(hipMemsetD32Async(fb[k], 0x3c003c00u, sb / 4, st));
     }
     Events ev;
     NDQ_HIP(hipEventCreate(&ev.e0));
     NDQ_HIP(hipEventCreate(&ev.e1));
     auto launch = [&](int k) -> int {
         const int s = k % nsets;
-        const int par = (k / nsets) & 1;   // alternate D_eo and D_oe
+        const int par = (k / nsets) & 1;   // alternate the direction of the hop
         ndq_gauge u = *U;
         u.data = links[s];
-        ndq_spinor in{par ? odd[s] : even[s], sprec, par ? NDQ_ODD : NDQ_EVEN, 1};
-        ndq_spinor o{par ? even[s] : odd[s], sprec, par ? NDQ_EVEN : NDQ_ODD, 1};
+        if (ny == 2) {
+            ndq_spinor in{par ? fb[s] : fa[s], sprec, NDQ_FULL, 1};
+            ndq_spinor o{par ? fa[s] : fb[s], sprec, NDQ_FULL, 1};
+            return ndq_apply_Q(g, &u, -1.0, &in, &o, stream);
+        }
+        ndq_spinor in{par ? fb[s] : fa[s], sprec, par ? NDQ_ODD : NDQ_EVEN, 1};
+        ndq_spinor o{par ? fa[s] : fb[s], sprec, par ? NDQ_EVEN : NDQ_ODD, 1};
         return ndq_apply_dslash(g, &u, &in, &o, stream);
     };
-    const Tuning saved = tuning(sprec, U->prec, U->recon);
+    const Tuning saved = launch_tuning(g->k, sprec, U->prec, U->recon, ny);
     memset(out, 0, sizeof(*out));
     double best = 1e300;
     int best_b = 0, best_x = 1;
     for (int b = 0; b < 4; ++b) {
         for (int x = 0; x < 2; ++x) {
-            Tuning& t = tuning(sprec, U->prec, U->recon);
+            Tuning t;
             t.block = kBlocks[b];
             t.xcd_remap = x;
+            set_launch_tuning(g->k, sprec, U->prec, U->recon, ny, t);
             double us = 0.0;
             if ((rc = time_launches(launch, std::min(8, 2 * nsets), reps, st, ev.e0, ev.e1, &us))) {
-                tuning(sprec, U->prec, U->recon) = saved;
+                set_launch_tuning(g->k, sprec, U->prec, U->recon, ny, saved);
                 return rc;
             }
             out->us[2 * b + x] = us;
@@ -208,14 +219,38 @@ extern "C" int ndq_autotune(const ndq_geom* g, const ndq_gauge* U, int sprec, in
         best_x = saved.xcd_remap;
         best = out->us[cur];
     }
-    Tuning& t = tuning(sprec, U->prec, U->recon);
+    Tuning t;
     t.block = best_b;
     t.xcd_remap = best_x;
+    set_launch_tuning(g->k, sprec, U->prec, U->recon, ny, t);
     out->block = best_b;
     out->xcd_remap = best_x;
     out->us_best = best;
     out->nsets = nsets;
     return NDQ_OK;
+}
+
+}  // namespace
+
+extern "C" size_t ndq_autotune_workspace_bytes(const ndq_geom* g, const ndq_gauge* U, int sprec, int64_t rotate_bytes) {
+    if (!g || !U || check_gauge(U) || sprec < NDQ_F64 || sprec > NDQ_F16) return 0;
+    return dslash_ws(g, U, sprec, dslash_sets(g, U, sprec, rotate_bytes, 1), 1);
+}
+
+extern "C" size_t ndq_autotune_q_workspace_bytes(const ndq_geom* g, const ndq_gauge* U, int sprec,
+                                                 int64_t rotate_bytes) {
+    if (!g || !U || check_gauge(U) || sprec < NDQ_F64 || sprec > NDQ_F16) return 0;
+    return dslash_ws(g, U, sprec, dslash_sets(g, U, sprec, rotate_bytes, 2), 2);
+}
+
+extern "C" int ndq_autotune(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, int64_t rotate_bytes, void* ws,
+                            size_t ws_bytes, ndq_tune_result* out, void* stream) {
+    return autotune_single(g, U, sprec, reps, rotate_bytes, ws, ws_bytes, out, stream, 1);
+}
+
+extern "C" int ndq_autotune_q(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, int64_t rotate_bytes,
+                              void* ws, size_t ws_bytes, ndq_tune_result* out, void* stream) {
+    return autotune_single(g, U, sprec, reps, rotate_bytes, ws, ws_bytes, out, stream, 2);
 }
 
 extern "C" size_t ndq_autotune_mrhs_workspace_bytes(const ndq_geom* g, int sprec, int nrhs, int ny) {

@@ -59,6 +59,11 @@ struct Tuning {
 // Per storage format (spinor precision, link precision, recon index 0/1/2 for
 // 18/12/8); set by ndq_set_launch / ndq_set_launch_for (the autotuner).
 Tuning& tuning(int sprec, int lprec, int recon);
+// The shape of one lattice and number of output parities (1: dslash, 2: Q):
+// the autotuner's choice for that lattice if it made one, else the format's.
+Tuning launch_tuning(const GeomK& g, int sprec, int lprec, int recon, int ny);
+void set_launch_tuning(const GeomK& g, int sprec, int lprec, int recon, int ny, const Tuning& t);
+void clear_launch_tuning(int sprec, int lprec, int recon);
 inline int recon_index(int recon) { return recon == 18 ? 0 : recon == 12 ? 1 : 2; }
 
 // Work order of the multi-right-hand-side stencil (see k_wilson_mrhs): rg
@@ -80,6 +85,7 @@ MrhsShape default_mrhs_shape(const GeomK& g, int sprec, int lprec, int recon, in
 
 WilsonArgs wilson_args(const ndq_geom* g, const ndq_gauge* U, int sprec);
 int wilson_blocks(const ndq_geom* g, int block, int ny);
+// block < 0: the shape and XCD remap of launch_tuning for this lattice and ny.
 hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& a, int ny, int block, hipStream_t st);
 // nrhs right-hand sides (a.in/out/self/v views point at rhs 0; rhs r at + r * rhs_bytes),
 // links staged once in LDS; epilogue with up to 3 extra vectors, no partial sums.

@@ -690,6 +690,11 @@ hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& args
     // full Q, whose larger per-site footprint gains from the slice-chunked
     // order (measured on 24^3 x 48; the F32 and F16 forms gain nothing).
     WilsonArgs a = args;
+    if (block < 0) {
+        const Tuning t = launch_tuning(a.g, sprec, lprec, recon, ny);
+        block = t.block;
+        a.xcd_remap = t.xcd_remap;
+    }
     if (ny == 2 && sprec == P64 && a.order_c == 0) a.order_c = tile_order(a.g, block == 0 ? 64 : block);
     const int key = sprec * 1000 + lprec * 100 + recon;
     switch (key) {
@@ -812,7 +817,7 @@ int ndq_apply_Q(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spino
         a.b_hop = -0.5;
         a.gamma5 = 1;
         if (batched) NDQ_HIP(launch_wilson_mrhs(in->prec, U->prec, U->recon, a, 2, in->nrhs, st));
-        else NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 2, tuning(in->prec, U->prec, U->recon).block, st));
+        else NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 2, -1, st));
     }
     return NDQ_OK;
 }
@@ -887,7 +892,7 @@ int ndq_apply_dslash(const ndq_geom* g, const ndq_gauge* U, const ndq_spinor* in
         a.b_hop = 1.0;
         a.gamma5 = 0;
         if (batched) NDQ_HIP(launch_wilson_mrhs(in->prec, U->prec, U->recon, a, 1, in->nrhs, st));
-        else NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 1, tuning(in->prec, U->prec, U->recon).block, st));
+        else NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 1, -1, st));
     }
     return NDQ_OK;
 }
@@ -912,7 +917,7 @@ int ndq_apply_Qhat_ee(const ndq_geom* g, const ndq_gauge* U, double m, const ndq
         a.in[0] = view_of(g, in, 0, r);
         a.out[0] = view_of(g, tmp, 1, r);
         a.b_hop = 1.0;
-        NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 1, tuning(in->prec, U->prec, U->recon).block, st));
+        NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, a, 1, -1, st));
         WilsonArgs b = wilson_args(g, U, in->prec);
         b.p0 = 0;
         b.in[0] = view_of(g, tmp, 1, r);
@@ -922,7 +927,7 @@ int ndq_apply_Qhat_ee(const ndq_geom* g, const ndq_gauge* U, double m, const ndq
         b.a_self = 4.0 + m;
         b.b_hop = -1.0 / (4.0 * (4.0 + m));
         b.gamma5 = 1;
-        NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, b, 1, tuning(in->prec, U->prec, U->recon).block, st));
+        NDQ_HIP(launch_wilson(in->prec, U->prec, U->recon, b, 1, -1, st));
     }
     return NDQ_OK;
 }

@@ -148,6 +148,10 @@ _SIG = {
     "ndq_autotune_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(_Gauge), ctypes.c_int, ctypes.c_int64]),
     "ndq_autotune": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.c_int, ctypes.c_int, ctypes.c_int64, _P, ctypes.c_size_t,
                           ctypes.POINTER(_TuneResult), _P]),
+    "ndq_autotune_q_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(_Gauge), ctypes.c_int, ctypes.c_int64]),
+    "ndq_autotune_q": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.c_int, ctypes.c_int, ctypes.c_int64, _P, ctypes.c_size_t,
+                            ctypes.POINTER(_TuneResult), _P]),
+    "ndq_get_launch_lattice": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "ndq_autotune_mrhs_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "ndq_autotune_mrhs": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P,
                                ctypes.c_size_t, ctypes.POINTER(_MrhsTuneResult), _P]),
@@ -239,15 +243,18 @@ def set_launch(block: int, xcd_remap: bool = True):
     _check(lib().ndq_set_launch(block, int(bool(xcd_remap))))
 
 
-def autotune(geom: "Geometry", U: "GaugeField", sprec: int, reps: int = 100, rotate_bytes: int = 0, stream=None) -> dict:
-    """Time every stencil launch shape for this format and keep the fastest."""
+def autotune(geom: "Geometry", U: "GaugeField", sprec: int, reps: int = 100, rotate_bytes: int = 0,
+             full_q: bool = False, stream=None) -> dict:
+    """Time every stencil launch shape of the dslash (or, with ``full_q``, of Q) on
+    this lattice and format, and keep the fastest for them."""
     r = _TuneResult()
-    n = int(lib().ndq_autotune_workspace_bytes(geom.handle, ctypes.byref(U.desc), int(sprec), int(rotate_bytes)))
+    pre = "ndq_autotune_q" if full_q else "ndq_autotune"
+    n = int(getattr(lib(), pre + "_workspace_bytes")(geom.handle, ctypes.byref(U.desc), int(sprec), int(rotate_bytes)))
     if n == 0:
-        raise NdqError(-1, "bad arguments for ndq_autotune_workspace_bytes")
+        raise NdqError(-1, f"bad arguments for {pre}_workspace_bytes")
     ws = torch.empty(n, dtype=torch.uint8, device="cuda")
-    _check(lib().ndq_autotune(geom.handle, ctypes.byref(U.desc), int(sprec), int(reps), int(rotate_bytes), _ptr(ws), n,
-                              ctypes.byref(r), _stream(stream)))
+    _check(getattr(lib(), pre)(geom.handle, ctypes.byref(U.desc), int(sprec), int(reps), int(rotate_bytes), _ptr(ws),
+                               n, ctypes.byref(r), _stream(stream)))
     del ws
     shapes = {f"block{b}_xcd{x}": r.us[2 * i + x] for i, b in enumerate((0, 64, 128, 256)) for x in (0, 1)}
     return {"block": r.block, "xcd_remap": r.xcd_remap, "us_best": r.us_best, "us": shapes, "nsets": r.nsets}
@@ -265,6 +272,14 @@ def autotune_mrhs(geom: "Geometry", U: "GaugeField", sprec: int, nrhs: int, ny: 
     _check(lib().ndq_autotune_mrhs(geom.handle, ctypes.byref(U.desc), int(sprec), int(nrhs), int(ny), int(reps),
                                    _ptr(ws), n, ctypes.byref(r), _stream(stream)))
     return r.as_dict()
+
+
+def get_launch_lattice(geom: "Geometry", sprec: int, lprec: int, recon: int, ny: int = 1) -> dict:
+    """The launch shape used on this lattice (the tuned one, else the format's)."""
+    b = ctypes.c_int()
+    x = ctypes.c_int()
+    _check(lib().ndq_get_launch_lattice(geom.handle, sprec, lprec, recon, ny, ctypes.byref(b), ctypes.byref(x)))
+    return {"block": b.value, "xcd_remap": x.value}
 
 
 def get_launch(sprec: int, lprec: int, recon: int) -> dict:

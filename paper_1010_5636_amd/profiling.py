@@ -295,7 +295,39 @@ def _modes24(reps):
     _log("modes24: done")
 
 
-WORKLOADS = {"fullq24": _fullq24, "mrhs32": _mrhs32, "filter24": _filter24, "modes24": _modes24}
+def _batch24(reps):
+    """The batched sign of the point-source solves: a degree-4 polynomial sign
+    (Clenshaw on the multi-RHS stencil) with 20 FP64 modes on a block of 12 F32
+    fields (12-real F32 links) on 24^3 x 48, sandwich projection (block Gram
+    products on the matrix cores, one-pass rank-20 update)."""
+    import torch
+    import synthetic
+    import paper_1010_5636_amd as ndq
+    import numpy as np
+    dims = (48, 24, 24, 24)
+    g = ndq.Geometry(dims)
+    U = ndq.GaugeField.pack(g, torch.from_numpy(synthetic.gauge_field(dims)).cuda(), ndq.F32, 12)
+    nev = 20
+    modes = ndq.SpinorField(g, ndq.F64, ndq.FULL, nev)
+    one = ndq.SpinorField.pack(g, torch.from_numpy(synthetic.spinor(g.volume)).cuda(), ndq.F64, ndq.FULL)
+    rb = g.spinor_bytes(ndq.F64, ndq.FULL, 1)
+    for r in range(nev):
+        modes.buf[r * rb:(r + 1) * rb].copy_(one.buf)
+    nu = np.linspace(-0.5, 0.5, nev) + 0.01
+    ov = ndq.Overlap(g, -1.4, ndq.Approx(ndq.MINMAX_POLY, 0.01, 4), 6.6, modes=modes, nu=nu, form=ndq.SANDWICH)
+    x = ndq.SpinorField(g, ndq.F32, ndq.FULL, 12)
+    x1 = ndq.SpinorField.pack(g, torch.from_numpy(synthetic.spinor(g.volume)).cuda(), ndq.F32, ndq.FULL)
+    rb = g.spinor_bytes(ndq.F32, ndq.FULL, 1)
+    for r in range(12):
+        x.buf[r * rb:(r + 1) * rb].copy_(x1.buf)
+    y = x.like()
+    for _ in range(reps):
+        ndq.apply_sign(g, U, ov, x, y)
+    torch.cuda.synchronize()
+    _log("batch24: done")
+
+
+WORKLOADS = {"fullq24": _fullq24, "mrhs32": _mrhs32, "filter24": _filter24, "modes24": _modes24, "batch24": _batch24}
 CALIBRATION_BYTES = 512 * 1024 * 1024
 
 

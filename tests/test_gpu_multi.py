@@ -104,12 +104,20 @@ def test_autotune_keeps_parity(fmt):
         # the fastest shape, or the one in use when it is within 3% of the fastest
         assert res["us_best"] <= 1.03 * min(res["us"].values())
         assert res["us_best"] == res["us"][f"block{res['block']}_xcd{res['xcd_remap']}"]
-        assert ndq.ndq.get_launch(sp, lp, recon) == {"block": res["block"], "xcd_remap": res["xcd_remap"]}
+        shape = {"block": res["block"], "xcd_remap": res["xcd_remap"]}
+        assert ndq.ndq.get_launch_lattice(L["g"], sp, lp, recon, 1) == shape
+        # other lattices keep the format's shape
+        other = ndq.Geometry((8, 8, 8, 8))
+        assert ndq.ndq.get_launch_lattice(other, sp, lp, recon, 1) == ndq.ndq.get_launch(sp, lp, recon)
+        resq = ndq.autotune(L["g"], L["U"], sp, reps=20, rotate_bytes=int(6e8), full_q=True)
+        assert ndq.ndq.get_launch_lattice(L["g"], sp, lp, recon, 2) == {"block": resq["block"],
+                                                                       "xcd_remap": resq["xcd_remap"]}
         ndq.apply_Q(L["g"], L["U"], M, L["x"], L["y"])
         got = L["y"].unpack().cpu().numpy()[0]
         assert rel_l2(got, dirac.apply_Q(L["u"], L["psi"][0], M, dims)) <= TOL[sp]
     finally:
         ndq.set_launch(0, 1)
+    assert ndq.ndq.get_launch_lattice(L["g"], sp, lp, recon, 1) == {"block": 0, "xcd_remap": 1}
 
 
 def test_multi_max_jobs():
