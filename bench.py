@@ -198,12 +198,9 @@ def solve_leg(log):
     torch.cuda.synchronize()
     t_fields = time.perf_counter() - t0
     log(f"solve leg: fields {t_fields:.1f} s")
-    # launch shapes of the solver's full-Q launches on this lattice, per format
+    # work order of the 12-field multi-RHS stencil of the batched solves
     tuned = {}
     t0 = time.perf_counter()
-    for name, sp, Uf in (("f32-r12", ndq.F32, U32), ("f16-r12", ndq.F16, U16), ("f64-r18", ndq.F64, U64)):
-        r = ndq.autotune(g, Uf, sp, reps=20, rotate_bytes=int(6e8), full_q=True)
-        tuned[name] = {"block": r["block"], "xcd_remap": r["xcd_remap"], "us_best": round(r["us_best"], 2)}
     for name, sp, Uf in (("f32-r12", ndq.F32, U32), ("f16-r12", ndq.F16, U16)):
         r = ndq.ndq.autotune_mrhs(g, Uf, sp, 12, ny=2, reps=5)
         tuned[name + "_12rhs"] = {k: r[k] for k in ("rg", "group_major", "chunk", "us_best", "us_previous")}
@@ -446,7 +443,7 @@ def batch_leg(log):
         "us": round(ms_d * 1e3, 3), "alg_bytes": alg_d, "gbs": round(alg_d / (ms_d * 1e-3) / 1e9, 1),
         "frac_hbm": round(alg_d / (ms_d * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "gflops": round(FLOP_PER_SITE * (v // 2) / (ms_d * 1e-3) / 1e9, 1),
-        "launch": {"block": tune["block"], "xcd_remap": tune["xcd_remap"]}}
+        "launch": {"block": tune["block"], "xcd_remap": tune["xcd_remap"], "chunked_order": tune["order"]}}
     log(f"batch leg: dslash 32^3x64 {ms_d * 1e3:.2f} us ({out['dslash_32c64']['frac_hbm']:.3f} of HBM peak)")
     del e, o, U12
     canon = torch.zeros((12, v, 4, 3), dtype=torch.complex128, device=dev)

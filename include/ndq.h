@@ -483,7 +483,9 @@ int ndq_get_launch_for(int sprec, int lprec, int recon, int* block, int* xcd_rem
 
 /* Autotuner of the launch shape: times `reps` even/odd dslash applies on
  * lattice g with links U and spinors of precision sprec for each launch shape
- * (block 0/64/128/256, XCD remap off/on), on ceil(rotate_bytes / set size)
+ * (block 0/64/128/256, XCD remap off/on, tiles in index order or in the
+ * slice-chunked order that keeps neighbouring time slices of a tile close in
+ * time), on ceil(rotate_bytes / set size)
  * rotating copies of (links, even spinor, odd spinor) so that consecutive
  * applies stream from HBM as in a solver (rotate_bytes <= 0: one set), and
  * records the fastest shape for dslash launches of that storage format on
@@ -503,6 +505,8 @@ typedef struct {
     double us_best;       /* its average time per dslash, microseconds               */
     double us[8];         /* every shape: index 2 * b + xcd_remap, b over 0/64/128/256 */
     int32_t nsets;        /* rotating sets used                                      */
+    int32_t order;        /* chosen tile order: 0 index order, 1 slice-chunked order  */
+    double us_order[8];   /* every shape with the slice-chunked tile order           */
 } ndq_tune_result;
 size_t ndq_autotune_workspace_bytes(const ndq_geom* g, const ndq_gauge* U, int sprec, int64_t rotate_bytes);
 int ndq_autotune(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, int64_t rotate_bytes, void* ws,

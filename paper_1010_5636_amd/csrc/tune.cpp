@@ -190,22 +190,27 @@ int autotune_single(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, 
     memset(out, 0, sizeof(*out));
     double best = 1e300;
     int best_b = 0, best_x = 1;
-    for (int b = 0; b < 4; ++b) {
-        for (int x = 0; x < 2; ++x) {
-            Tuning t;
-            t.block = kBlocks[b];
-            t.xcd_remap = x;
-            set_launch_tuning(g->k, sprec, U->prec, U->recon, ny, t);
-            double us = 0.0;
-            if ((rc = time_launches(launch, std::min(8, 2 * nsets), reps, st, ev.e0, ev.e1, &us))) {
-                set_launch_tuning(g->k, sprec, U->prec, U->recon, ny, saved);
-                return rc;
-            }
-            out->us[2 * b + x] = us;
-            if (us < best) {
-                best = us;
-                best_b = kBlocks[b];
-                best_x = x;
+    int best_o = 0;
+    for (int o = 0; o < 2; ++o) {
+        for (int b = 0; b < 4; ++b) {
+            for (int x = 0; x < 2; ++x) {
+                Tuning t;
+                t.block = kBlocks[b];
+                t.xcd_remap = x;
+                t.order = o;
+                set_launch_tuning(g->k, sprec, U->prec, U->recon, ny, t);
+                double us = 0.0;
+                if ((rc = time_launches(launch, std::min(8, 2 * nsets), reps, st, ev.e0, ev.e1, &us))) {
+                    set_launch_tuning(g->k, sprec, U->prec, U->recon, ny, saved);
+                    return rc;
+                }
+                (o ? out->us_order : out->us)[2 * b + x] = us;
+                if (us < best) {
+                    best = us;
+                    best_b = kBlocks[b];
+                    best_x = x;
+                    best_o = o;
+                }
             }
         }
     }
@@ -214,17 +219,21 @@ int autotune_single(const ndq_geom* g, const ndq_gauge* U, int sprec, int reps, 
     int cur = 0;
     for (int b = 0; b < 4; ++b)
         if (kBlocks[b] == saved.block) cur = 2 * b + saved.xcd_remap;
-    if (out->us[cur] <= 1.03 * best) {
+    const double cur_us = (saved.order ? out->us_order : out->us)[cur];
+    if (cur_us <= 1.03 * best) {
         best_b = saved.block;
         best_x = saved.xcd_remap;
-        best = out->us[cur];
+        best_o = saved.order;
+        best = cur_us;
     }
     Tuning t;
     t.block = best_b;
     t.xcd_remap = best_x;
+    t.order = best_o;
     set_launch_tuning(g->k, sprec, U->prec, U->recon, ny, t);
     out->block = best_b;
     out->xcd_remap = best_x;
+    out->order = best_o;
     out->us_best = best;
     out->nsets = nsets;
     return NDQ_OK;

@@ -55,6 +55,7 @@ struct MultiArgs {
 struct Tuning {
     int block = 0;
     int xcd_remap = 1;
+    int order = 0;    // 1: tiles in the slice-chunked order of tile_order (autotuner only)
 };
 // Per storage format (spinor precision, link precision, recon index 0/1/2 for
 // 18/12/8); set by ndq_set_launch / ndq_set_launch_for (the autotuner).

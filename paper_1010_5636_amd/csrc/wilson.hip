@@ -694,6 +694,7 @@ hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& args
         const Tuning t = launch_tuning(a.g, sprec, lprec, recon, ny);
         block = t.block;
         a.xcd_remap = t.xcd_remap;
+        if (t.order && a.order_c == 0) a.order_c = tile_order(a.g, block == 0 ? 64 : block);
     }
     if (ny == 2 && sprec == P64 && a.order_c == 0) a.order_c = tile_order(a.g, block == 0 ? 64 : block);
     const int key = sprec * 1000 + lprec * 100 + recon;

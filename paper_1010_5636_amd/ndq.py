@@ -51,7 +51,8 @@ class _QJob(ctypes.Structure):
 
 class _TuneResult(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("us_best", ctypes.c_double),
-                ("us", ctypes.c_double * 8), ("nsets", ctypes.c_int32)]
+                ("us", ctypes.c_double * 8), ("nsets", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("us_order", ctypes.c_double * 8)]
 
 
 class _MrhsTuneResult(ctypes.Structure):
@@ -257,7 +258,10 @@ def autotune(geom: "Geometry", U: "GaugeField", sprec: int, reps: int = 100, rot
                                n, ctypes.byref(r), _stream(stream)))
     del ws
     shapes = {f"block{b}_xcd{x}": r.us[2 * i + x] for i, b in enumerate((0, 64, 128, 256)) for x in (0, 1)}
-    return {"block": r.block, "xcd_remap": r.xcd_remap, "us_best": r.us_best, "us": shapes, "nsets": r.nsets}
+    shapes.update({f"block{b}_xcd{x}_chunked": r.us_order[2 * i + x] for i, b in enumerate((0, 64, 128, 256))
+                   for x in (0, 1)})
+    return {"block": r.block, "xcd_remap": r.xcd_remap, "order": r.order, "us_best": r.us_best, "us": shapes,
+            "nsets": r.nsets}
 
 
 def autotune_mrhs(geom: "Geometry", U: "GaugeField", sprec: int, nrhs: int, ny: int = 2, reps: int = 10,

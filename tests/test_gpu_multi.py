@@ -103,7 +103,8 @@ def test_autotune_keeps_parity(fmt):
         assert all(t > 0 for t in res["us"].values())
         # the fastest shape, or the one in use when it is within 3% of the fastest
         assert res["us_best"] <= 1.03 * min(res["us"].values())
-        assert res["us_best"] == res["us"][f"block{res['block']}_xcd{res['xcd_remap']}"]
+        suffix = "_chunked" if res["order"] else ""
+        assert res["us_best"] == res["us"][f"block{res['block']}_xcd{res['xcd_remap']}{suffix}"]
         shape = {"block": res["block"], "xcd_remap": res["xcd_remap"]}
         assert ndq.ndq.get_launch_lattice(L["g"], sp, lp, recon, 1) == shape
         # other lattices keep the format's shape
