@@ -41,6 +41,8 @@ constexpr double kUpperMargin = 0.05;   // |eps| <= 1 + delta: A_s <= 2 + delta
 // the interval [floor, 2] stays damped and the block still converges into
 // the null space (and is then reported as too small).
 constexpr double kCutoffFloor = 1e-2;
+// Fields per block sign application (the block sign takes at most NDQ_MAX_BATCH).
+constexpr int kSignBlock = NDQ_MAX_BATCH;
 
 struct IxCtx {
     const ndq_geom* g;
@@ -55,10 +57,16 @@ struct IxCtx {
     int64_t signs = 0;
 
     ndq_spinor vec(char* base, int i) const { return ndq_spinor{base + (int64_t)i * vb, NDQ_F64, NDQ_FULL, 1}; }
+    // fields i .. i+n-1 of a block, as one descriptor
+    ndq_spinor vecs(char* base, int i, int n) const {
+        return ndq_spinor{base + (int64_t)i * vb, NDQ_F64, NDQ_FULL, n};
+    }
 
+    // out = sign(Q) in for every field of the block `in` (one block sign: the
+    // stencil applications of the recurrence serve all its fields)
     int sign(const ndq_spinor* in, const ndq_spinor* out) {
         Arena ar{sign_ws, sign_bytes};
-        ++signs;
+        signs += in->nrhs;
         return apply_sign(g, U, p, in, out, ar, nullptr, st);
     }
     int norm2(const ndq_spinor* x, double* out) {
@@ -87,11 +95,14 @@ struct IxCtx {
 
 // out = ax x + bA (A_s x) + cw w   (w optional; out may alias x or w):
 // A_s x = x + (s/2) eps x + (1/2) gamma5 eps x for a chirality-s vector x.
+// x, out and w may be blocks of up to kSignBlock fields.
 int as_combo(IxCtx& c, int s, const ndq_spinor* x, const ndq_spinor* out, double ax, double bA,
              const ndq_spinor* w = nullptr, double cw = 0.0) {
-    int rc = c.sign(x, &c.S);
+    ndq_spinor S = c.S;
+    S.nrhs = x->nrhs;
+    int rc = c.sign(x, &S);
     if (rc) return rc;
-    const ndq_spinor* v[4] = {x, &c.S, &c.S, w};
+    const ndq_spinor* v[4] = {x, &S, &S, w};
     const Coef cf[4] = {Coef{ax + bA, nullptr}, Coef{0.5 * s * bA, nullptr}, Coef{0.5 * bA, nullptr},
                         Coef{cw, nullptr}};
     const int g5[4] = {0, 0, 1, 0};
@@ -114,18 +125,20 @@ int copy(IxCtx& c, const ndq_spinor* dst, const ndq_spinor* src) {
 
 // F_j = T_d(A~) X_j for every vector of the block, A~ = (2 A_s - (a + b)) / (b - a).
 // T_{k+1} = 2 A~ T_k - T_{k-1} overwrites T_{k-1}; X is destroyed.
+// The vectors go through in sub-blocks of up to kSignBlock fields.
 int filter(IxCtx& c, int s, char* X, char* F, int nb, double a, double b, int d) {
     const double c1 = 2.0 / (b - a), c2 = -(a + b) / (b - a);
     int rc;
-    for (int j = 0; j < nb; ++j) {
-        ndq_spinor tp = c.vec(X, j), tc = c.vec(F, j);
+    for (int j = 0; j < nb; j += kSignBlock) {
+        const int n = std::min(kSignBlock, nb - j);
+        ndq_spinor tp = c.vecs(X, j, n), tc = c.vecs(F, j, n);
         if ((rc = as_combo(c, s, &tp, &tc, c2, c1))) return rc;   // T_1
         for (int k = 2; k <= d; ++k) {
             if ((rc = as_combo(c, s, &tc, &tp, 2.0 * c2, 2.0 * c1, &tp, -1.0))) return rc;
             std::swap(tp, tc);
         }
         if (tc.data != F + (int64_t)j * c.vb) {
-            const ndq_spinor fj = c.vec(F, j);
+            const ndq_spinor fj = c.vecs(F, j, n);
             if ((rc = copy(c, &fj, &tc))) return rc;
         }
     }
@@ -183,8 +196,9 @@ int adaptive_degree(double a, double b) {
 // vectors and free1, free2 the two blocks no longer needed.
 int rayleigh_ritz(IxCtx& c, int s, char*& X, char*& free1, char*& free2, int nb, Sector& sec) {
     int rc;
-    for (int j = 0; j < nb; ++j) {
-        const ndq_spinor xj = c.vec(X, j), wj = c.vec(free1, j);
+    for (int j = 0; j < nb; j += kSignBlock) {
+        const int n = std::min(kSignBlock, nb - j);
+        const ndq_spinor xj = c.vecs(X, j, n), wj = c.vecs(free1, j, n);
         if ((rc = as_combo(c, s, &xj, &wj, 0.0, 1.0))) return rc;
     }
     std::vector<cd> M, Z;
@@ -267,11 +281,12 @@ void with_defaults(const ndq_index_params* in, ndq_index_params& ip) {
 }
 
 size_t index_workspace(const ndq_geom* g, const ndq_overlap_params* p, const ndq_index_params& ip) {
+    const int nsb = std::min(kSignBlock, ip.block);
     Arena ar{nullptr, 0};
-    ar.take(sign_workspace(g, p, NDQ_F64));
+    ar.take(sign_workspace(g, p, NDQ_F64, nsb));
     const size_t vb = (size_t)spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
     for (int k = 0; k < 3; ++k) ar.take(vb * ip.block);
-    ar.take(vb);
+    ar.take(vb * nsb);
     ar.take(vb);
     ar.take(gram_partials_bytes(g, ip.block, ip.block));
     ar.take(sizeof(cd) * 64 * 64);
@@ -328,11 +343,12 @@ int ndq_index_DN(const ndq_geom* g, const ndq_gauge* U, const ndq_overlap_params
     c.p = p;
     c.st = st;
     c.vb = spinor_rhs_bytes(g, NDQ_F64, NDQ_FULL);
-    c.sign_bytes = sign_workspace(g, p, NDQ_F64);
+    const int nsb = std::min(kSignBlock, ip.block);
+    c.sign_bytes = sign_workspace(g, p, NDQ_F64, nsb);
     c.sign_ws = static_cast<char*>(ar.take(c.sign_bytes));
     char* B[3];
     for (int k = 0; k < 3; ++k) B[k] = static_cast<char*>(ar.take((size_t)c.vb * ip.block));
-    c.S = ws_spinor(ar, g, NDQ_F64);
+    c.S = ws_block(ar, g, NDQ_F64, nsb);
     c.R = ws_spinor(ar, g, NDQ_F64);
     c.gpart = static_cast<double*>(ar.take(gram_partials_bytes(g, ip.block, ip.block)));
     c.G = static_cast<double*>(ar.take(sizeof(cd) * 64 * 64));

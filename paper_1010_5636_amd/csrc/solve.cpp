@@ -83,6 +83,24 @@ int host_norm2(const ndq_geom* g, const ndq_spinor* x, double* partials, double*
 
 Coef hc(double v) { return Coef{v, nullptr}; }
 
+// Coefficients of D = alpha + beta gamma5 eps: alpha = 1/abar + mq/2, beta = 1/abar - mq/2.
+double d_alpha(const DOp& d) { return -d.p->m + 0.5 * d.p->mq; }
+double d_beta(const DOp& d) { return -d.p->m - 0.5 * d.p->mq; }
+
+// out = D^H y = alpha y + beta eps (gamma5 y) with the operator of d; tmp: work field.
+int dh_apply(DOp& d, const ndq_spinor* y, const ndq_spinor* tmp, const ndq_spinor* out) {
+    const ndq_spinor* src[2] = {y, nullptr};
+    Coef cf[2] = {hc(1.0), hc(0.0)};
+    const int g5[2] = {1, 0};
+    int rc = lincomb(d.g, d.prec, tmp, 1, src, cf, g5, nullptr, d.st);
+    if (!rc) rc = sign_apply(d, tmp);
+    if (rc) return rc;
+    src[1] = &d.S;
+    cf[0] = hc(d_alpha(d));
+    cf[1] = hc(d_beta(d));
+    return lincomb(d.g, d.prec, out, 2, src, cf, nullptr, nullptr, d.st);
+}
+
 // CGNE for D e = rhs (all in d.prec); e starts at zero.  Returns iterations.
 int cgne(DOp& d, const ndq_spinor* rhs, Vecs& v, double tol, int max_iter, double* partials, double* dscal,
          int* iters) {
@@ -99,16 +117,9 @@ int cgne(DOp& d, const ndq_spinor* rhs, Vecs& v, double tol, int max_iter, doubl
     if ((rc = lincomb(g, d.prec, &v.s, 1, src, cf, nullptr, nullptr, st))) return rc;
     double r0;
     if ((rc = host_norm2(g, &v.s, partials, dscal, &r0, st))) return rc;
-    // z = D^H s = g5 D g5 s
-    auto dh = [&](const ndq_spinor* in, const ndq_spinor* out) {
-        const ndq_spinor* s1[1] = {in};
-        const Coef c1[1] = {hc(1.0)};
-        const int g1[1] = {1};
-        int r = lincomb(g, d.prec, &v.t, 1, s1, c1, g1, nullptr, st);
-        if (!r) r = d_apply(d, &v.t, out);
-        if (!r) r = lincomb(g, d.prec, out, 1, &out, c1, g1, nullptr, st);
-        return r;
-    };
+    // z = D^H s = alpha s + beta eps (gamma5 s): one gamma5 pass before the sign
+    // and the combination after it (gamma5 D gamma5 would take one more pass)
+    auto dh = [&](const ndq_spinor* in, const ndq_spinor* out) { return dh_apply(d, in, &v.t, out); };
     if ((rc = dh(&v.s, &v.z))) return rc;
     src[0] = &v.z;
     if ((rc = lincomb(g, d.prec, &v.p, 1, src, cf, nullptr, nullptr, st))) return rc;
@@ -150,10 +161,6 @@ int cgne(DOp& d, const ndq_spinor* rhs, Vecs& v, double tol, int max_iter, doubl
     *iters = it;
     return NDQ_OK;
 }
-
-// Coefficients of D = alpha + beta gamma5 eps: alpha = 1/abar + mq/2, beta = 1/abar - mq/2.
-double d_alpha(const DOp& d) { return -d.p->m + 0.5 * d.p->mq; }
-double d_beta(const DOp& d) { return -d.p->m - 0.5 * d.p->mq; }
 
 // out = H_s in = (alpha^2 + beta^2) in + 2 s alpha beta P_s eps in, for a chirality-s `in`
 // (2 s alpha beta P_s S = s alpha beta S + alpha beta gamma5 S).
@@ -256,21 +263,6 @@ int sectors_solve(DOp& d, const ndq_spinor* rhs, Vecs& v, double tol, int max_it
         if ((rc = lincomb(g, d.prec, &v.t, 2, acc, ca, nullptr, nullptr, st))) return rc;
     }
     return NDQ_OK;
-}
-
-// out = D^H y = alpha y + beta eps (gamma5 y) with the operator of d (F64 fields);
-// tmp: work field.
-int dh_apply(DOp& d, const ndq_spinor* y, const ndq_spinor* tmp, const ndq_spinor* out) {
-    const ndq_spinor* src[2] = {y, nullptr};
-    Coef cf[2] = {hc(1.0), hc(0.0)};
-    const int g5[2] = {1, 0};
-    int rc = lincomb(d.g, d.prec, tmp, 1, src, cf, g5, nullptr, d.st);
-    if (!rc) rc = sign_apply(d, tmp);
-    if (rc) return rc;
-    src[1] = &d.S;
-    cf[0] = hc(d_alpha(d));
-    cf[1] = hc(d_beta(d));
-    return lincomb(d.g, d.prec, out, 2, src, cf, nullptr, nullptr, d.st);
 }
 
 // Inner relative residual when the caller leaves it open: half the target in
