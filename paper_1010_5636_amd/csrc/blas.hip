@@ -602,10 +602,10 @@ __global__ void k_mode_coef_block(const double* c, const double* d, ModeSigns sg
 
 // out_r = in_r + sum_k coef[k][r] u_k for a block of fields (r < nr), one lane
 // per (complex component c, site s) with sites fastest, so that every load is
-// a contiguous run of one plane; for F32 output the two components of one
-// 16-byte word sit in adjacent lanes (lane pair = site, lane parity =
-// component), so each word is written whole by one store instruction.  The
-// fields come in groups of kRotJ laid out over the wavefronts of a workgroup as
+// a contiguous run of one plane (measured faster than pairing the two
+// components of an F32 word in one lane or in adjacent lanes, although the
+// halves of a word are then stored by different wavefronts).  The fields come
+// in groups of kRotJ laid out over the wavefronts of a workgroup as
 // in k_rotate, so the mode planes leave HBM once.  The sum runs in the order
 // of k_mode_update (start from in, add the modes in index order, FP64).  PI:
 // precision of `in` (F64, F32 or F16); PO: precision of `out` (F64 or F32; an
@@ -620,17 +620,8 @@ __global__ void __launch_bounds__(256) k_mode_update_block(const char* __restric
     const int wave = threadIdx.x >> 6;
     const int64_t t = ((int64_t)blockIdx.x * wpg + wave % wpg) * 64 + (threadIdx.x & 63);
     if (t >= 12 * (int64_t)n) return;
-    int c;
-    int32_t s;
-    if constexpr (PO == P32) {
-        const int64_t pr = t >> 1;   // (plane j, site s) pair
-        const int j = (int)(pr / n);
-        s = (int32_t)(pr - (int64_t)j * n);
-        c = 2 * j + (int)(t & 1);
-    } else {
-        c = (int)(t / n);
-        s = (int32_t)(t - (int64_t)c * n);
-    }
+    const int c = (int)(t / n);
+    const int32_t s = (int32_t)(t - (int64_t)c * n);
     const int r0 = kRotJ * (wave / wpg);
     const int cnt = min(kRotJ, nr - r0);
     C<double> acc[kRotJ];

@@ -4,6 +4,7 @@
     python -m paper_1010_5636_amd.profiling traffic <out.json> <copy_bytes> <cmd> <block,xcd>=<fetch_dir>,<write_dir> ...
     python -m paper_1010_5636_amd.profiling kernels <out.txt> <copy_bytes> <cmd> <trace_dir> <fetch_dir> <write_dir>
     python -m paper_1010_5636_amd.profiling run <workload>[,<workload>...] [reps]
+    python -m paper_1010_5636_amd.profiling dispatches <out.txt> <copy_bytes> <cmd> <pattern> <trace_dir> <counter>=<dir> ...
 
 ``run`` executes fixed, seeded workloads of the solve and batching legs for the
 profiler (``WORKLOADS`` below), each a few launches of the kernels it names,
@@ -327,7 +328,75 @@ def _batch24(reps):
     _log("batch24: done")
 
 
-WORKLOADS = {"fullq24": _fullq24, "mrhs32": _mrhs32, "filter24": _filter24, "modes24": _modes24, "batch24": _batch24}
+# Work orders of the multi-RHS stencil compared by ``_orders32`` (fields per
+# workgroup, group-major, tile chunk): the default, the tuned orders and the
+# one-field-per-group extreme.
+ORDERS32 = [(0, 0, -1), (6, 1, 16), (4, 1, 16), (2, 1, 16), (1, 1, 16), (12, 0, 16)]
+
+
+def _orders32(reps):
+    """The 12-field Q apply of ``_mrhs32`` (random fields) in each work order
+    of ORDERS32, `reps` applies each, in that order (for per-dispatch counters)."""
+    import torch
+    import synthetic
+    import paper_1010_5636_amd as ndq
+    from paper_1010_5636_amd import ndq as nb
+    dims = (64, 32, 32, 32)
+    g = ndq.Geometry(dims)
+    U = ndq.GaugeField.pack(g, torch.from_numpy(synthetic.gauge_field(dims)).cuda(), ndq.F32, 18)
+    x = ndq.SpinorField(g, ndq.F32, ndq.FULL, 12)
+    gen = torch.Generator(device="cuda").manual_seed(1002)
+    x.buf.view(torch.float32).normal_(generator=gen)   # in place: no copy kernel besides the calibration
+    y = x.like()
+    for rg, gm, ch in ORDERS32:
+        nb.set_mrhs_launch(g, ndq.F32, ndq.F32, 18, 12, 2, rg, bool(gm), ch, True, -1)
+        for _ in range(reps):
+            ndq.apply_Q(g, U, -1.4, x, y)
+        torch.cuda.synchronize()
+        _log(f"orders32: rg={rg} group_major={gm} chunk={ch} done")
+
+
+WORKLOADS = {"fullq24": _fullq24, "mrhs32": _mrhs32, "filter24": _filter24, "modes24": _modes24, "batch24": _batch24,
+             "orders32": _orders32}
+
+
+def dispatches_text(trace_dir: str, pmc_dirs, copy_bytes: int, pattern: str, labels, command: str) -> str:
+    """Per-dispatch duration and counters of the kernels whose name contains
+    `pattern`, in dispatch order, grouped `len(dispatches) / len(labels)` per
+    label.  pmc_dirs: [(counter, dir)]; FETCH_SIZE and WRITE_SIZE are scaled to
+    bytes by the calibration copy, other counters are printed as read."""
+    import sqlite3
+    durs = []
+    for path in _dbs(trace_dir):
+        con = sqlite3.connect(path)
+        durs += [d for (d,) in con.execute("select duration from kernels where name like ? order by id",
+                                           (f"%{pattern}%",))]
+        con.close()
+    cols = []
+    for counter, d in pmc_dirs:
+        vals = counters(d, counter)
+        seq = [v for name, vs in vals.items() if pattern in name for v in vs]
+        scale = 1.0
+        if counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            c = _copy_reading(vals, copy_bytes)
+            scale = copy_bytes / c / 1e6 if c else float("nan")
+        cols.append((counter, [v * scale for v in seq]))
+    per = max(1, len(durs) // max(1, len(labels)))
+    lines = ["# rocprofv3 per-dispatch kernel time and counters", f"# command: {command}",
+             f"# kernel source hash: {kernel_hash()}", f"# kernels matching: {pattern}",
+             "# FETCH_SIZE / WRITE_SIZE in MB (scaled by a device copy of %d bytes); other counters raw" % copy_bytes,
+             "", f"{'label':<28}{'us':>10}" + "".join(f"{c:>16}" for c, _ in cols)]
+    for i, lab in enumerate(labels):
+        sl = slice(i * per, (i + 1) * per)
+        t = sorted(durs[sl])
+        if not t:
+            continue
+        row = f"{str(lab):<28}{t[len(t) // 2] / 1e3:>10.1f}"
+        for _, v in cols:
+            vv = sorted(v[sl]) if len(v) >= (i + 1) * per else []
+            row += f"{vv[len(vv) // 2]:>16.1f}" if vv else f"{'-':>16}"
+        lines.append(row)
+    return "\n".join(lines) + "\n"
 CALIBRATION_BYTES = 512 * 1024 * 1024
 
 
@@ -376,6 +445,15 @@ def main(argv):
         return run(argv[1].split(","), int(argv[2]) if len(argv) > 2 else 10)
     if len(argv) == 7 and argv[0] == "kernels":
         txt = kernels_text(argv[4], argv[5], argv[6], int(argv[2]), argv[3])
+        with open(argv[1], "w") as fh:
+            fh.write(txt)
+        print(txt)
+        return 0
+    if len(argv) >= 6 and argv[0] == "dispatches":
+        # dispatches <out.txt> <copy_bytes> <cmd> <pattern> <trace_dir> <counter>=<dir> ...
+        pmc = [tuple(a.split("=", 1)) for a in argv[6:]]
+        labels = [f"rg={a} gm={b} chunk={c}" for a, b, c in ORDERS32]
+        txt = dispatches_text(argv[5], pmc, int(argv[2]), argv[4], labels, argv[3])
         with open(argv[1], "w") as fh:
             fh.write(txt)
         print(txt)
