@@ -176,7 +176,7 @@ def poly_for(ndq, eps, target):
         n += max(4, n // 10)
 
 
-def solve_leg(log):
+def solve_leg(log, sectors_fp64=False):
     """D_N^m solves on the 24^3 x 48 lattice: mixed precision (F32 arithmetic on
     F32 or F16 storage, FP64 defect correction) vs plain FP64, to a 1e-10 true
     relative residual.  Setup (fields, 20 FP64 low modes, approximants) is timed
@@ -240,14 +240,15 @@ def solve_leg(log):
     point[0, 2, 0] = 1.0
     b_point = ndq.SpinorField.pack(g, point, ndq.F64, ndq.FULL)
     del point
-    for name, prec, Ulo, ovlo, itol, sectors, rhs in (
-            ("mixed_f32", ndq.F32, U32, ov_lo, 0.0, False, b),
-            ("mixed_f16", ndq.F16, U16, ov_lo, 0.0, False, b),
-            ("fp64", ndq.F64, None, None, 0.0, False, b),
-            ("point_mixed_f32", ndq.F32, U32, ov_lo, 0.0, False, b_point),
-            ("point_mixed_f32_sectors", ndq.F32, U32, ov_lo, 0.0, True, b_point),
-            ("point_fp64", ndq.F64, None, None, 0.0, False, b_point),
-            ("point_fp64_sectors", ndq.F64, None, None, 0.0, True, b_point)):
+    cases = [("mixed_f32", ndq.F32, U32, ov_lo, 0.0, False, b),
+             ("mixed_f16", ndq.F16, U16, ov_lo, 0.0, False, b),
+             ("fp64", ndq.F64, None, None, 0.0, False, b),
+             ("point_mixed_f32", ndq.F32, U32, ov_lo, 0.0, False, b_point),
+             ("point_mixed_f32_sectors", ndq.F32, U32, ov_lo, 0.0, True, b_point)]
+    if sectors_fp64:   # the plain-FP64 pair of the inner-solver comparison (38 s)
+        cases += [("point_fp64", ndq.F64, None, None, 0.0, False, b_point),
+                  ("point_fp64_sectors", ndq.F64, None, None, 0.0, True, b_point)]
+    for name, prec, Ulo, ovlo, itol, sectors, rhs in cases:
         x = ndq.SpinorField(g, ndq.F64, ndq.FULL)
         x.buf.zero_()
         torch.cuda.synchronize()
@@ -341,8 +342,10 @@ def solve_leg(log):
     out["speedup_mixed_f32_vs_fp64"] = round(runs["fp64"]["seconds"] / runs["mixed_f32"]["seconds"], 3)
     out["speedup_mixed_f16_vs_fp64"] = round(runs["fp64"]["seconds"] / runs["mixed_f16"]["seconds"], 3)
     out["speedup_sectors_vs_cgne_point_source"] = {
-        "mixed_f32": round(runs["point_mixed_f32"]["seconds"] / runs["point_mixed_f32_sectors"]["seconds"], 3),
-        "fp64": round(runs["point_fp64"]["seconds"] / runs["point_fp64_sectors"]["seconds"], 3)}
+        "mixed_f32": round(runs["point_mixed_f32"]["seconds"] / runs["point_mixed_f32_sectors"]["seconds"], 3)}
+    if sectors_fp64:
+        out["speedup_sectors_vs_cgne_point_source"]["fp64"] = round(
+            runs["point_fp64"]["seconds"] / runs["point_fp64_sectors"]["seconds"], 3)
     return out
 
 
@@ -682,6 +685,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run a device-to-device copy of BYTES bytes (counter calibration)")
     ap.add_argument("--no-solve", action="store_true", help="skip the 24^3x48 D_N solve leg")
+    ap.add_argument("--sectors-fp64", action="store_true",
+                    help="also run the plain-FP64 CGNE / chirality-sector comparison on a point source")
     ap.add_argument("--no-extra", action="store_true", help="skip the batching, graph and autograd legs")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--launch", default="", metavar="BLOCK,XCD",
@@ -884,7 +889,7 @@ def main():
     }
     log = lambda msg: print(msg, file=sys.stderr, flush=True)  # noqa: E731
     if not args.no_solve:
-        out["dn_solve"] = solve_leg(log)
+        out["dn_solve"] = solve_leg(log, args.sectors_fp64)
     if not args.no_extra:
         out["batching"] = batch_leg(log)
         out["graph_multishift"] = graph_leg(log)
