@@ -467,7 +467,10 @@ int ndq_set_launch_for(int sprec, int lprec, int recon, int block, int xcd_remap
  * workgroup of 64 sites (0: all nrhs; the links of a tile are staged in LDS
  * once per workgroup), group_major = 1 runs every tile for one group of rg
  * fields before the next group (the neighbour spinors re-read by nearby tiles
- * then stay in the caches), 0 runs the groups of a tile next to each other;
+ * then stay in the caches), 0 runs the groups of a tile next to each other,
+ * 2 gives each XCD one group and one part of the tiles (the number of groups
+ * must divide 8, else group-major is used): the XCDs walk the same tiles
+ * together, sharing the links through the last-level cache;
  * chunk: -1 automatic, 0 tiles in index order, c > 0 c consecutive tiles of
  * every time slice in turn (c must divide the 64-site tiles of a slice);
  * xcd_remap as in ndq_set_launch; link_nt: links loaded with the non-temporal

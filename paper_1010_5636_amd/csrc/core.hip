@@ -279,7 +279,7 @@ extern "C" int ndq_set_mrhs_launch(const ndq_geom* g, int sprec, int lprec, int 
     }
     ndq::MrhsShape s;
     s.rg = rg;
-    s.group_major = group_major ? 1 : 0;
+    s.group_major = group_major == 2 ? 2 : group_major ? 1 : 0;
     s.chunk = chunk;
     s.xcd_remap = xcd_remap ? 1 : 0;
     s.link_nt = link_nt < 0 ? -1 : (link_nt ? 1 : 0);

@@ -529,28 +529,42 @@ __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int
 // re-read by neighbouring tiles are then those of rg fields only, so they stay
 // in L2; links are read once per group); tile-major order runs the groups of a
 // tile next to each other (they share the tile's links in L2).
+// XCD-group order (group_major = 2, ngroups dividing 8): workgroup b runs on
+// XCD b mod 8 (the dispatcher's round robin); XCD x takes group x mod ngroups
+// and part x / ngroups of the tile list, in order.  The XCDs holding the same
+// part walk the same tiles at about the same time, so each tile's links come
+// from HBM once and from the shared last-level cache for the other groups,
+// while each XCD's L2 holds the neighbour spinors of its own rg fields only.
 struct MrhsGrid {
     int32_t tiles;       // tiles of 64 sites per parity
     int ny;              // output parities (1 or 2)
     int rg;              // right-hand sides per workgroup
     int ngroups;
-    int group_major;
+    int group_major;     // 0 tile-major, 1 group-major, 2 XCD groups
     int nrhs;
+    int32_t per_part;    // XCD groups: tile positions per part
 };
 
 template <int SP, int LP, int RECON, bool NT>
 __global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, MrhsGrid m) {
     extern __shared__ uint32_t lw[];   // [8 dirs][link words][64 sites]
-    unsigned lin = blockIdx.x;
-    if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x);
     const unsigned per_group = (unsigned)(m.ny * m.tiles);
     unsigned grp, rem;
-    if (m.group_major) {
-        grp = lin / per_group;
-        rem = lin - grp * per_group;
+    if (m.group_major == 2) {
+        const unsigned x = blockIdx.x & 7u, k = blockIdx.x >> 3;
+        grp = x % (unsigned)m.ngroups;
+        rem = (x / (unsigned)m.ngroups) * (unsigned)m.per_part + k;
+        if (rem >= per_group) return;   // the whole workgroup: before any barrier
     } else {
-        rem = lin / (unsigned)m.ngroups;
-        grp = lin - rem * (unsigned)m.ngroups;
+        unsigned lin = blockIdx.x;
+        if (a.xcd_remap) lin = xcd_remap(lin, gridDim.x);
+        if (m.group_major) {
+            grp = lin / per_group;
+            rem = lin - grp * per_group;
+        } else {
+            rem = lin / (unsigned)m.ngroups;
+            grp = lin - rem * (unsigned)m.ngroups;
+        }
     }
     int y = 0;
     int32_t pos = (int32_t)rem;
@@ -587,7 +601,8 @@ hipError_t allow_lds(K kernel, size_t lds) {
 
 template <int SP, int LP, int RECON, bool NT>
 hipError_t launch_mrhs_nt(const WilsonArgs& a, const MrhsGrid& m, hipStream_t st) {
-    const dim3 grid((unsigned)((int64_t)m.tiles * m.ny * m.ngroups));
+    const dim3 grid(m.group_major == 2 ? (unsigned)(8 * (int64_t)m.per_part)
+                                       : (unsigned)((int64_t)m.tiles * m.ny * m.ngroups));
     const size_t lds = mrhs_lds_bytes<SP, LP, RECON>();
     const hipError_t e = allow_lds(&k_wilson_mrhs<SP, LP, RECON, NT>, lds);
     if (e != hipSuccess) return e;
@@ -729,6 +744,15 @@ hipError_t launch_wilson_mrhs(int sprec, int lprec, int recon, const WilsonArgs&
     m.ngroups = (nrhs + m.rg - 1) / m.rg;
     m.group_major = sh.group_major;
     m.nrhs = nrhs;
+    m.per_part = 0;
+    if (m.group_major == 2) {
+        if (8 % m.ngroups != 0) {
+            m.group_major = 1;   // XCD groups need a number of groups dividing 8
+        } else {
+            const int parts = 8 / m.ngroups;
+            m.per_part = (int32_t)((m.tiles * (int64_t)ny + parts - 1) / parts);
+        }
+    }
     const int key = sprec * 1000 + lprec * 100 + recon;
     switch (key) {
         case P64 * 1000 + P64 * 100 + 18: return launch_mrhs_fmt<P64, P64, 18>(a, m, sh.link_nt, st);

@@ -295,9 +295,10 @@ def get_launch(sprec: int, lprec: int, recon: int) -> dict:
 
 
 def set_mrhs_launch(geom: "Geometry", sprec: int, lprec: int, recon: int, nrhs: int, ny: int, rg: int = 0,
-                    group_major: bool = False, chunk: int = -1, xcd_remap: bool = True, link_nt: int = -1):
-    """Work order of the multi-right-hand-side stencil for one lattice, format, nrhs and ny."""
-    _check(lib().ndq_set_mrhs_launch(geom.handle, sprec, lprec, recon, nrhs, ny, rg, int(bool(group_major)), chunk,
+                    group_major: int = 0, chunk: int = -1, xcd_remap: bool = True, link_nt: int = -1):
+    """Work order of the multi-right-hand-side stencil for one lattice, format, nrhs and ny
+    (group_major: 0 tile-major, 1 group-major, 2 one group per XCD)."""
+    _check(lib().ndq_set_mrhs_launch(geom.handle, sprec, lprec, recon, nrhs, ny, rg, int(group_major), chunk,
                                      int(bool(xcd_remap)), int(link_nt)))
 
 

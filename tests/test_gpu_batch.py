@@ -153,10 +153,11 @@ def test_point_sources_32c64():
 
 
 @pytest.mark.parametrize("shape", [(0, 0, -1, 1, -1), (1, 1, 0, 1, -1), (3, 1, 2, 0, 1), (5, 0, 4, 1, 0),
-                                   (6, 1, 4, 1, -1), (12, 1, 8, 1, 1)])
+                                   (6, 1, 4, 1, -1), (12, 1, 8, 1, 1), (3, 2, 4, 1, -1), (6, 2, 0, 1, -1),
+                                   (5, 2, -1, 1, -1)])
 def test_work_order_does_not_change_results(shape):
     """Every work order of the multi-RHS stencil (fields per workgroup, group-
-    or tile-major order, tile chunk, XCD remap, link load hint) gives the same
+    or tile-major order, one group per XCD, tile chunk, XCD remap, link load hint) gives the same
     bits: 12 fields of Q on an 8x8x8x16 lattice (8 tiles of 64 sites per time
     slice; ragged last group for 5 per group), and the even/odd hopping block
     on the same fields."""
@@ -171,8 +172,8 @@ def test_work_order_does_not_change_results(shape):
     outs = {}
     for label, sh in (("default", None), ("shape", shape)):
         if sh is not None:
-            ndq.ndq.set_mrhs_launch(g, ndq.F32, ndq.F32, 12, 12, 2, rg, bool(gm), chunk, bool(xcd), nt)
-            ndq.ndq.set_mrhs_launch(g, ndq.F32, ndq.F32, 12, 12, 1, rg, bool(gm), chunk, bool(xcd), nt)
+            ndq.ndq.set_mrhs_launch(g, ndq.F32, ndq.F32, 12, 12, 2, rg, gm, chunk, bool(xcd), nt)
+            ndq.ndq.set_mrhs_launch(g, ndq.F32, ndq.F32, 12, 12, 1, rg, gm, chunk, bool(xcd), nt)
         y = x.like()
         ndq.apply_Q(g, U, M, x, y)
         ye = xo.like(parity=ndq.EVEN)
