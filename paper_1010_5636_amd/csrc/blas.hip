@@ -418,7 +418,8 @@ __global__ void __launch_bounds__(256) k_rotate(const char* __restrict__ src, in
                                                 int32_t n) {
     const int ng = (k + kRotJ - 1) / kRotJ;
     const int wpg = rot_wpg(ng);
-    const int wave = threadIdx.x >> 6;
+    // wavefront index, wave-uniform: the group's coefficients are then scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t = ((int64_t)blockIdx.x * wpg + wave % wpg) * 64 + (threadIdx.x & 63);
     if (t >= 12 * (int64_t)n) return;
     const int c = (int)(t / n);
@@ -511,7 +512,7 @@ __global__ void __launch_bounds__(256) k_gram(const char* __restrict__ A, int na
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x;   // the chunk
     if (wave >= nchunks) return;
-    const int ti = threadIdx.x >> 6;
+    const int ti = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform row tile
     const int t = lane & 15, kk = lane >> 4;
     const int ntj = (nb + 15) / 16;
     const int NI = 16 * ((na + 15) / 16), NJ = 16 * ntj;
@@ -617,7 +618,8 @@ __global__ void __launch_bounds__(256) k_mode_update_block(const char* __restric
                                                            SpinorView in, SpinorView out, int32_t n) {
     const int ng = (nr + kRotJ - 1) / kRotJ;
     const int wpg = rot_wpg(ng);
-    const int wave = threadIdx.x >> 6;
+    // wavefront index, wave-uniform: the group's coefficients are then scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t = ((int64_t)blockIdx.x * wpg + wave % wpg) * 64 + (threadIdx.x & 63);
     if (t >= 12 * (int64_t)n) return;
     const int c = (int)(t / n);
