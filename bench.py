@@ -189,7 +189,9 @@ def solve_leg(log, sectors_fp64=False):
     g = ndq.Geometry(SOLVE_DIMS)
     v = g.volume
     u = torch.from_numpy(synthetic.gauge_field(SOLVE_DIMS)).to(dev)
-    U64 = ndq.GaugeField.pack(g, u, ndq.F64, 18)
+    # FP64 links in the 12-real form (c = (a x b)^*, Eq. 3): exact for SU(3) to FP64 rounding,
+    # a third fewer link bytes for the FP64 operator, the low-mode filter and the plain solve
+    U64 = ndq.GaugeField.pack(g, u, ndq.F64, 12)
     U32 = ndq.GaugeField.pack(g, u, ndq.F32, 12)
     U16 = ndq.GaugeField.pack(g, u, ndq.F16, 12)
     del u
@@ -310,9 +312,9 @@ def solve_leg(log, sectors_fp64=False):
     del b12, x1
     torch.cuda.empty_cache()
     # algorithmic bytes of the Q applies alone (links once, spinor in and out
-    # once per apply: 384 B/site F32-12, 200 F16-12, 960 F64-18), counted at the
+    # once per apply: 384 B/site F32-12, 200 F16-12, 768 F64-12), counted at the
     # inner precision for the mixed runs (the FP64 outer applies are ~2% of them)
-    qbytes = {"mixed_f32": 384, "mixed_f16": 200, "fp64": 960}
+    qbytes = {"mixed_f32": 384, "mixed_f16": 200, "fp64": 768}
     for name, r in runs.items():
         rb = r["q_applies"] * qbytes["mixed_f32" if "f32" in name else "fp64" if "fp64" in name else name] * v
         r["q_alg_bytes"] = rb
