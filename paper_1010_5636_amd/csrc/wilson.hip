@@ -406,12 +406,56 @@ __global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
     }
 }
 
+// Links of a multi-right-hand-side tile in LDS, per direction a block of
+// planes of 64 sites (lane l touches consecutive words).  F32/F16 links are
+// decoded to 18 reals once per tile (the 12- and 8-real reconstructions then
+// run once per link, not once per right-hand side); FP64 links stay in their
+// stored words and are decoded per right-hand side, which keeps the LDS of a
+// 12-real FP64 tile at 48 KiB.
+template <int LP, int RECON>
+struct StagedLinks {
+    using LR = typename LinkReal<LP>::R;
+    static constexpr bool kDecoded = LP != P64;
+    static constexpr int kWords = kDecoded ? 18 : LinkFmt<LP, RECON>::kWords;
+    __device__ static __forceinline__ void put(uint32_t* lw, int dir, int lane, const uint32_t words[]) {
+        if constexpr (kDecoded) {
+            C<LR> u[3][3];
+            link_decode<LP, RECON>(words, u);
+            float* d = reinterpret_cast<float*>(lw) + dir * 18 * 64 + lane;
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    d[(2 * (3 * r + c)) * 64] = u[r][c].r;
+                    d[(2 * (3 * r + c) + 1) * 64] = u[r][c].i;
+                }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kWords; ++k) lw[(dir * kWords + k) * 64 + lane] = words[k];
+        }
+    }
+    __device__ static __forceinline__ void get(const uint32_t* lw, int dir, int lane, C<LR> u[3][3]) {
+        if constexpr (kDecoded) {
+            const float* d = reinterpret_cast<const float*>(lw) + dir * 18 * 64 + lane;
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) u[r][c] = {d[(2 * (3 * r + c)) * 64], d[(2 * (3 * r + c) + 1) * 64]};
+        } else {
+            uint32_t words[kWords];
+#pragma unroll
+            for (int k = 0; k < kWords; ++k) words[k] = lw[(dir * kWords + k) * 64 + lane];
+            link_decode<LP, RECON>(words, u);
+        }
+    }
+};
+
 // Many right-hand sides on one gauge field: a workgroup of 4 wavefronts owns
 // 64 output sites; it first stages the 8 links of each site into LDS (forward
-// links at the tile's own sites, backward links at the neighbours, 32-bit words
-// with the site index fastest), then wavefront q computes right-hand sides
-// q, q+4, q+8, ... for the 64 sites, decoding links from LDS.  Links leave HBM
-// once per apply instead of once per right-hand side; every spinor load of a
+// links at the tile's own sites, backward links at the neighbours; see
+// StagedLinks), then wavefront q computes right-hand sides q, q+4, q+8, ... for
+// the 64 sites, reading the links from LDS.  Links leave HBM once per apply
+// instead of once per right-hand side; every spinor load of a
 // wavefront is one right-hand side's 64 consecutive sites.  The per-site
 // arithmetic is that of k_wilson (same hop order and epilogue), so results
 // match the one-lane-per-site kernel bit for bit.
@@ -425,26 +469,25 @@ template <int SP, int LP, int RECON, bool NT>
 __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int p, int32_t tile,
                                           const SpinorView& in, const SpinorView* self, const SpinorView& out,
                                           double a_self, double b_hop, int gamma5, double c0d, int r0, int r1,
-                                          uint32_t* lw, int nv = 0, const SpinorView* v = nullptr,
-                                          const double* cvd = nullptr) {
+                                          uint32_t* lw, int nv = 0, const SpinorView* v = nullptr, int vstride = 1,
+                                          const Coef* cv = nullptr) {
     using R = typename SpinorIO<SP>::R;
-    using F = LinkFmt<LP, RECON>;
+    using LR = typename LinkReal<LP>::R;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int32_t i = tile * 64 + lane;
     const bool active = i < g.vh;
     int32_t nb[8];
+    using SL = StagedLinks<LP, RECON>;
     if (active) {
         const SiteCoord x = eo_coords(g, p, i);
         eo_neighbours(g, i, x, nb);
         // wavefront w stages the forward link mu = w and the backward link mu = w
-        uint32_t words[F::kWords];
+        uint32_t words[LinkFmt<LP, RECON>::kWords];
         link_load_words<LP, RECON, NT>(links, g.vh, p * 4 + w, i, words);
-#pragma unroll
-        for (int k = 0; k < F::kWords; ++k) lw[(w * F::kWords + k) * 64 + lane] = words[k];
+        SL::put(lw, w, lane, words);
         link_load_words<LP, RECON, NT>(links, g.vh, (1 - p) * 4 + w, nb[4 + w], words);
-#pragma unroll
-        for (int k = 0; k < F::kWords; ++k) lw[((4 + w) * F::kWords + k) * 64 + lane] = words[k];
+        SL::put(lw, 4 + w, lane, words);
     }
     __syncthreads();
     if (!active) return;
@@ -465,24 +508,19 @@ __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
             C<R> sf[12], sb[12];
-            C<typename LinkReal<LP>::R> u[3][3];
-            uint32_t words[F::kWords];
+            C<LR> u[3][3];
             SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[mu], sf);
             if constexpr (SP != P64) {
                 SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[4 + mu], sb);
                 __builtin_amdgcn_sched_barrier(0);
             }
-#pragma unroll
-            for (int k = 0; k < F::kWords; ++k) words[k] = lw[(mu * F::kWords + k) * 64 + lo];
-            link_decode<LP, RECON>(words, u);
+            SL::get(lw, mu, lo, u);
             if (mu == 0) hop_fwd<0>(sf, u, acc);
             if (mu == 1) hop_fwd<1>(sf, u, acc);
             if (mu == 2) hop_fwd<2>(sf, u, acc);
             if (mu == 3) hop_fwd<3>(sf, u, acc);
             if constexpr (SP == P64) SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[4 + mu], sb);
-#pragma unroll
-            for (int k = 0; k < F::kWords; ++k) words[k] = lw[((4 + mu) * F::kWords + k) * 64 + lo];
-            link_decode<LP, RECON>(words, u);
+            SL::get(lw, 4 + mu, lo, u);
             if (mu == 0) hop_bwd<0>(sb, u, acc);
             if (mu == 1) hop_bwd<1>(sb, u, acc);
             if (mu == 2) hop_bwd<2>(sb, u, acc);
@@ -509,11 +547,11 @@ __device__ __forceinline__ void mrhs_tile(const GeomK& g, const char* links, int
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = cscale(c0, acc[k]);
         for (int j = 0; j < nv; ++j) {
-            SpinorView vj = v[j];
+            SpinorView vj = v[j * vstride];
             vj.base += (int64_t)r * vj.rhs_bytes;
             C<R> vv[12];
             SpinorIO<SP>::load(vj, (int64_t)vj.site0 + i, vv);
-            const R cj = (R)cvd[j];
+            const R cj = (R)coef(cv[j]);
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = {acc[k].r + cj * vv[k].r, acc[k].i + cj * vv[k].i};
         }
@@ -547,7 +585,7 @@ struct MrhsGrid {
 
 template <int SP, int LP, int RECON, bool NT>
 __global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, MrhsGrid m) {
-    extern __shared__ uint32_t lw[];   // [8 dirs][link words][64 sites]
+    extern __shared__ uint32_t lw[];   // [8 dirs][StagedLinks words][64 sites]
     const unsigned per_group = (unsigned)(m.ny * m.tiles);
     unsigned grp, rem;
     if (m.group_major == 2) {
@@ -575,19 +613,13 @@ __global__ void __launch_bounds__(256) k_wilson_mrhs(WilsonArgs a, MrhsGrid m) {
     const int32_t tile = order_tile(pos, m.tiles, a.g.n0, a.order_c);
     const int r0 = (int)grp * m.rg;
     const int r1 = min(m.nrhs, r0 + m.rg);
-    SpinorView vv[3];
-    double cv[3];
-    for (int j = 0; j < a.nv; ++j) {
-        vv[j] = a.v[j][y];
-        cv[j] = coef(a.cv[j]);
-    }
     mrhs_tile<SP, LP, RECON, NT>(a.g, a.links, a.p0 + y, tile, a.in[y], a.has_self ? &a.self[y] : nullptr, a.out[y],
-                                 a.a_self, a.b_hop, a.gamma5, coef(a.c0), r0, r1, lw, a.nv, vv, cv);
+                                 a.a_self, a.b_hop, a.gamma5, coef(a.c0), r0, r1, lw, a.nv, &a.v[0][y], 2, a.cv);
 }
 
 template <int SP, int LP, int RECON>
 size_t mrhs_lds_bytes() {
-    return (size_t)8 * LinkFmt<LP, RECON>::kWords * 64 * sizeof(uint32_t);
+    return (size_t)8 * StagedLinks<LP, RECON>::kWords * 64 * sizeof(uint32_t);
 }
 
 // FP64 18-real links need 72 KiB of LDS per workgroup (of the 160 KiB per CU):
