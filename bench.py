@@ -450,6 +450,29 @@ def batch_leg(log):
         "gflops": round(FLOP_PER_SITE * (v // 2) / (ms_d * 1e-3) / 1e9, 1),
         "launch": {"block": tune["block"], "xcd_remap": tune["xcd_remap"], "chunked_order": tune["order"]}}
     log(f"batch leg: dslash 32^3x64 {ms_d * 1e3:.2f} us ({out['dslash_32c64']['frac_hbm']:.3f} of HBM peak)")
+    # the same with 18-real links (no reconstruction; 768 B per site)
+    tune18 = ndq.autotune(g, U, ndq.F32, reps=50)
+    par18 = {"k": 0}
+
+    def dslash_big18():
+        if par18["k"] % 2 == 0:
+            ndq.apply_dslash(g, U, e, o)
+        else:
+            ndq.apply_dslash(g, U, o, e)
+        par18["k"] += 1
+
+    for _ in range(10):
+        dslash_big18()
+    ms_d18 = _time_events(dslash_big18, 200)
+    alg_d18 = 768 * (v // 2)
+    out["dslash_32c64_r18"] = {
+        "workload": "even/odd dslash, 32^3x64, F32 spinors, 18-real F32 links, random SU(3) links (width 0.3)",
+        "us": round(ms_d18 * 1e3, 3), "alg_bytes": alg_d18, "gbs": round(alg_d18 / (ms_d18 * 1e-3) / 1e9, 1),
+        "frac_hbm": round(alg_d18 / (ms_d18 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "gflops": round(FLOP_PER_SITE * (v // 2) / (ms_d18 * 1e-3) / 1e9, 1),
+        "launch": {"block": tune18["block"], "xcd_remap": tune18["xcd_remap"], "chunked_order": tune18["order"]}}
+    log(f"batch leg: dslash 32^3x64 18-real {ms_d18 * 1e3:.2f} us "
+        f"({out['dslash_32c64_r18']['frac_hbm']:.3f} of HBM peak)")
     del e, o, U12
     canon = torch.zeros((12, v, 4, 3), dtype=torch.complex128, device=dev)
     for s in range(4):
