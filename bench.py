@@ -541,6 +541,8 @@ def batch_leg(log):
 
     multi()
     separate()
+    # the persistent grid (a multiple of the resident workgroups) picked by its autotuner
+    grid_tune = ndq.ndq.autotune_multi(sets[0], reps=20)
     ms_m = _time_events(multi, 30)
     ms_sep = _time_events(separate, 30)
     alg_m = nsites * (4 * 192 + 4 * 48)
@@ -548,8 +550,11 @@ def batch_leg(log):
         "workload": "Q on 8^4 + 12^4 + 16^3x32 at 4 RHS each, F32 spinors, 12-real F32 links",
         "sites": nsites, "persistent_ms": round(ms_m, 4), "separate_ms": round(ms_sep, 4),
         "speedup": round(ms_sep / ms_m, 3), "alg_bytes": alg_m,
-        "persistent_hbm_gbs": round(alg_m / (ms_m * 1e-3) / 1e9, 1)}
-    log(f"batch leg: multi-lattice persistent {ms_m:.4f} ms vs separate {ms_sep:.4f} ms")
+        "persistent_hbm_gbs": round(alg_m / (ms_m * 1e-3) / 1e9, 1),
+        "grid_factor": grid_tune["factor"],
+        "autotune_grid_us": {str(f): round(u, 2) for f, u in grid_tune["us"].items()}}
+    log(f"batch leg: multi-lattice persistent {ms_m:.4f} ms (grid factor {grid_tune['factor']}) vs separate "
+        f"{ms_sep:.4f} ms")
     return out
 
 

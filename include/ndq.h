@@ -149,9 +149,9 @@ int ndq_apply_Q(const ndq_geom* g, const ndq_gauge* U, double m, const ndq_spino
  * computed from them), so its results equal that call's bit for bit (and, for
  * nrhs = 1, those of the one-lane-per-site launch shape, block 64/128/256).
  * All jobs share the spinor precision and the link format; 1 <= njobs <= 8;
- * in, out: NDQ_FULL, same precision and nrhs, not aliased.  A fixed grid (four
- * times the workgroups the device holds at once) walks the joint tile list in
- * contiguous chunks.  Asynchronous. */
+ * in, out: NDQ_FULL, same precision and nrhs, not aliased.  A fixed grid (a
+ * multiple, ndq_set_multi_grid, of the workgroups the device holds at once)
+ * walks the joint tile list in contiguous chunks.  Asynchronous. */
 typedef struct {
     const ndq_geom* g;
     const ndq_gauge* U;
@@ -545,6 +545,28 @@ typedef struct {
 size_t ndq_autotune_mrhs_workspace_bytes(const ndq_geom* g, int sprec, int nrhs, int ny);
 int ndq_autotune_mrhs(const ndq_geom* g, const ndq_gauge* U, int sprec, int nrhs, int ny, int reps, void* ws,
                       size_t ws_bytes, ndq_mrhs_tune_result* out, void* stream);
+
+/* Grid of the persistent multi-lattice launch (ndq_apply_Q_multi): `factor`
+ * times the workgroups the device holds at once, 1 <= factor <= 16 (default 4).
+ * Process-wide; results do not depend on it (each tile is computed the same
+ * way whichever workgroup takes it).  Errors: NDQ_EINVAL. */
+int ndq_set_multi_grid(int factor);
+int ndq_get_multi_grid(void);
+
+/* Autotuner of that grid for one set of jobs (as ndq_apply_Q_multi): times
+ * `reps` launches at each factor of 1, 2, 3, 4, 6, 8 and 12 on the jobs' own
+ * fields (every launch writes out = Q in, so the outputs end as one
+ * ndq_apply_Q_multi would leave them), and sets the fastest, keeping the
+ * factor in use unless another is more than 3% faster.  No workspace.
+ * Synchronises `stream`.  Errors: those of ndq_apply_Q_multi, NDQ_EHIP. */
+typedef struct {
+    int32_t factor;       /* chosen factor                                             */
+    int32_t nfactors;     /* factors timed (us[0 .. nfactors-1], in the order above)   */
+    double us[8];         /* time per launch at each factor, microseconds              */
+    double us_best;       /* of the chosen factor                                      */
+    double us_previous;   /* of the factor in use before the call                      */
+} ndq_multi_tune_result;
+int ndq_autotune_multi(const ndq_q_job* jobs, int32_t njobs, int reps, ndq_multi_tune_result* out, void* stream);
 
 /* Gram matrix of two blocks of fields, G[i][j] = <A_i, B_j> = sum over sites and
  * spin-colour components of conj(A_i) B_j (the inner products of the

@@ -12,8 +12,12 @@
 // (ndq_set_mrhs_launch).  With NDQ_TUNE_CACHE naming a file, a key found
 // there is applied without timing, and new results are appended to it.
 //
-// Both time back-to-back launches between two events on the caller's stream,
-// on fields in the caller's workspace.
+// ndq_autotune_multi: the grid factor of the persistent multi-lattice launch
+// for one set of jobs.
+//
+// All time back-to-back launches between two events on the caller's stream,
+// on fields in the caller's workspace (the multi-lattice tuner: on the jobs'
+// own fields).
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -357,5 +361,57 @@ extern "C" int ndq_autotune_mrhs(const ndq_geom* g, const ndq_gauge* U, int spre
     out->us_best = best;
     out->us_previous = saved_us;
     out->nshapes = n;
+    return NDQ_OK;
+}
+
+// ---- grid of the persistent multi-lattice launch ---------------------------
+
+extern "C" int ndq_set_multi_grid(int factor) {
+    if (factor < 1 || factor > 16) return fail(NDQ_EINVAL, "ndq_set_multi_grid: factor %d outside 1..16", factor);
+    set_multi_grid_factor(factor);
+    return NDQ_OK;
+}
+
+extern "C" int ndq_get_multi_grid(void) { return multi_grid_factor(); }
+
+extern "C" int ndq_autotune_multi(const ndq_q_job* jobs, int32_t njobs, int reps, ndq_multi_tune_result* out,
+                                  void* stream) {
+    if (!out) return fail(NDQ_EINVAL, "ndq_autotune_multi: NULL result");
+    if (reps < 1) return fail(NDQ_EINVAL, "ndq_autotune_multi: reps must be >= 1");
+    memset(out, 0, sizeof(*out));
+    hipStream_t st = as_stream(stream);
+    const int saved = multi_grid_factor();
+    // one launch first: checks the jobs before any timing
+    int rc = ndq_apply_Q_multi(jobs, njobs, stream);
+    if (rc) return rc;
+    Events ev;
+    NDQ_HIP(hipEventCreate(&ev.e0));
+    NDQ_HIP(hipEventCreate(&ev.e1));
+    auto launch = [&](int) -> int { return ndq_apply_Q_multi(jobs, njobs, stream); };
+    const int factors[7] = {1, 2, 3, 4, 6, 8, 12};
+    double saved_us = 0.0;
+    set_multi_grid_factor(saved);
+    if ((rc = time_launches(launch, 2, reps, st, ev.e0, ev.e1, &saved_us))) return rc;
+    int best_f = saved;
+    double best = saved_us;
+    for (int k = 0; k < 7; ++k) {
+        set_multi_grid_factor(factors[k]);
+        double us = 0.0;
+        if ((rc = time_launches(launch, 2, reps, st, ev.e0, ev.e1, &us))) {
+            set_multi_grid_factor(saved);
+            return rc;
+        }
+        out->us[k] = us;
+        // a new factor must beat the one in use by more than 3%
+        if (us < best && us < saved_us / 1.03) {
+            best = us;
+            best_f = factors[k];
+        }
+    }
+    set_multi_grid_factor(best_f);
+    out->factor = best_f;
+    out->nfactors = 7;
+    out->us_best = best;
+    out->us_previous = saved_us;
     return NDQ_OK;
 }

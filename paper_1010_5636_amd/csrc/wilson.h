@@ -91,6 +91,11 @@ hipError_t launch_wilson(int sprec, int lprec, int recon, const WilsonArgs& a, i
 // nrhs right-hand sides (a.in/out/self/v views point at rhs 0; rhs r at + r * rhs_bytes),
 // links staged once in LDS; epilogue with up to 3 extra vectors, no partial sums.
 hipError_t launch_wilson_multi(int sprec, int lprec, int recon, const MultiArgs& a, hipStream_t st);
+// Workgroups of the persistent multi-lattice launch as a multiple of what the
+// device holds at once (1..16; 4 unless set by ndq_set_multi_grid or the
+// autotuner).
+int multi_grid_factor();
+void set_multi_grid_factor(int f);
 hipError_t launch_wilson_mrhs(int sprec, int lprec, int recon, const WilsonArgs& a, int ny, int nrhs, hipStream_t st);
 
 }  // namespace ndq

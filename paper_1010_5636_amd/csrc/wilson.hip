@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "wilson.h"
 
@@ -677,6 +678,8 @@ __global__ void __launch_bounds__(256) k_wilson_multi(MultiArgs a) {
     }
 }
 
+std::atomic<int> g_multi_grid{4};
+
 template <int SP, int LP, int RECON>
 hipError_t launch_multi_fmt(const MultiArgs& a, hipStream_t st) {
     const size_t lds = mrhs_lds_bytes<SP, LP, RECON>();
@@ -689,10 +692,10 @@ hipError_t launch_multi_fmt(const MultiArgs& a, hipStream_t st) {
     if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), 256, lds)) !=
         hipSuccess)
         return e;
-    // four times the workgroups the device holds at once (measured: one
+    // a multiple (default 4) of the workgroups the device holds at once: one
     // resident set walking long chunks leaves each workgroup a serial chain of
-    // memory round trips; a 4x grid overlaps them and still bounds the grid)
-    const int grid = std::max(1, std::min(a.total, 4 * std::max(1, per_cu) * cus));
+    // memory round trips; a larger grid overlaps them and still bounds the grid
+    const int grid = std::max(1, std::min(a.total, multi_grid_factor() * std::max(1, per_cu) * cus));
     hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(256), lds, st, a);
     return hipGetLastError();
 }
@@ -803,6 +806,9 @@ hipError_t launch_wilson_mrhs(int sprec, int lprec, int recon, const WilsonArgs&
         default: return hipErrorInvalidValue;
     }
 }
+
+int multi_grid_factor() { return g_multi_grid.load(std::memory_order_relaxed); }
+void set_multi_grid_factor(int f) { g_multi_grid.store(f, std::memory_order_relaxed); }
 
 hipError_t launch_wilson_multi(int sprec, int lprec, int recon, const MultiArgs& a, hipStream_t st) {
     const int key = sprec * 1000 + lprec * 100 + recon;

@@ -64,6 +64,16 @@ class _MrhsTuneResult(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class _MultiTuneResult(ctypes.Structure):
+    _fields_ = [("factor", ctypes.c_int32), ("nfactors", ctypes.c_int32), ("us", ctypes.c_double * 8),
+                ("us_best", ctypes.c_double), ("us_previous", ctypes.c_double)]
+
+    def as_dict(self):
+        facs = (1, 2, 3, 4, 6, 8, 12)
+        return {"factor": self.factor, "us": {f: self.us[k] for k, f in enumerate(facs[:self.nfactors])},
+                "us_best": self.us_best, "us_previous": self.us_previous}
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("m", ctypes.c_double), ("mq", ctypes.c_double), ("lam_max", ctypes.c_double),
                 ("approx", ctypes.c_void_p), ("modes", ctypes.c_void_p), ("nu", ctypes.POINTER(ctypes.c_double)),
@@ -159,6 +169,9 @@ _SIG = {
     "ndq_gram_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_int]),
     "ndq_spinor_gram": (_I, [_P, ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P, _P, ctypes.c_size_t, _P]),
     "ndq_apply_Q_multi": (_I, [ctypes.POINTER(_QJob), ctypes.c_int32, _P]),
+    "ndq_set_multi_grid": (_I, [_I]),
+    "ndq_get_multi_grid": (_I, []),
+    "ndq_autotune_multi": (_I, [ctypes.POINTER(_QJob), ctypes.c_int32, _I, ctypes.POINTER(_MultiTuneResult), _P]),
     "ndq_apply_dslash": (_I, [_P, ctypes.POINTER(_Gauge), ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor), _P]),
     "ndq_apply_Qhat_ee": (_I, [_P, ctypes.POINTER(_Gauge), _D, ctypes.POINTER(_Spinor), ctypes.POINTER(_Spinor),
                                ctypes.POINTER(_Spinor), _P]),
@@ -429,14 +442,35 @@ def spinor_gram(geom: Geometry, A: SpinorField, B: SpinorField, stream=None) -> 
     return G
 
 
-def apply_Q_multi(jobs, stream=None):
-    """Q on several lattices in one persistent launch: ``jobs`` is a list of
-    (geom, U, m, inp, out) tuples (NDQ_FULL fields, shared formats)."""
+def _q_jobs(jobs):
     arr = (_QJob * len(jobs))()
     for k, (geom, U, m, inp, out) in enumerate(jobs):
         arr[k] = _QJob(geom.handle, ctypes.pointer(U.desc), float(m), ctypes.pointer(inp.desc),
                        ctypes.pointer(out.desc))
-    _check(lib().ndq_apply_Q_multi(arr, len(jobs), _stream(stream)))
+    return arr
+
+
+def apply_Q_multi(jobs, stream=None):
+    """Q on several lattices in one persistent launch: ``jobs`` is a list of
+    (geom, U, m, inp, out) tuples (NDQ_FULL fields, shared formats)."""
+    _check(lib().ndq_apply_Q_multi(_q_jobs(jobs), len(jobs), _stream(stream)))
+
+
+def set_multi_grid(factor: int):
+    """Grid of the persistent multi-lattice launch, in multiples of the resident workgroups."""
+    _check(lib().ndq_set_multi_grid(int(factor)))
+
+
+def get_multi_grid() -> int:
+    return int(lib().ndq_get_multi_grid())
+
+
+def autotune_multi(jobs, reps: int = 20, stream=None) -> dict:
+    """Time the multi-lattice launch of ``jobs`` at each grid factor and keep the fastest
+    (the jobs' outputs end as one apply_Q_multi leaves them)."""
+    r = _MultiTuneResult()
+    _check(lib().ndq_autotune_multi(_q_jobs(jobs), len(jobs), int(reps), ctypes.byref(r), _stream(stream)))
+    return r.as_dict()
 
 
 def apply_dslash(geom: Geometry, U: GaugeField, inp: SpinorField, out: SpinorField, stream=None):

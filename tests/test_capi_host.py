@@ -73,6 +73,19 @@ def test_set_launch_validation(ndq):
     ndq.set_launch(0, True)
 
 
+def test_multi_grid_validation(ndq):
+    """The persistent launch's grid factor: 1..16, process-wide, default 4."""
+    assert ndq.get_multi_grid() == 4
+    for bad in (0, -1, 17):
+        with pytest.raises(ndq.NdqError):
+            ndq.set_multi_grid(bad)
+    try:
+        ndq.set_multi_grid(16)
+        assert ndq.get_multi_grid() == 16
+    finally:
+        ndq.set_multi_grid(4)
+
+
 def test_descriptor_validation_before_launch(ndq):
     """Bad descriptors fail on the host (no device memory is touched)."""
     lib = ndq.lib()

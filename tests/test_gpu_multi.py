@@ -136,6 +136,42 @@ def test_multi_max_jobs():
         ndq.apply_Q_multi([(L["g"], L["U"], L["m"], L["x"], L["y"]) for L in lats + [extra]])
 
 
+def test_multi_grid_factor_and_autotuner():
+    """Every grid factor of the persistent launch gives the same bits (the tiles
+    are computed alike whichever workgroup walks them); the grid autotuner picks
+    one of its factors and leaves the outputs of one apply."""
+    lats = [lattice(d, 4, s, ndq.F32, ndq.F32, 12) for d, s in (((8, 8, 8, 8), 81), ((12, 12, 12, 12), 82),
+                                                                ((32, 16, 16, 16), 83))]
+    jobs = [(L["g"], L["U"], L["m"], L["x"], L["y"]) for L in lats]
+    ref = []
+    try:
+        ndq.ndq.set_multi_grid(4)
+        ndq.apply_Q_multi(jobs)
+        ref = [L["y"].buf.clone() for L in lats]
+        for f in (1, 2, 3, 8, 12, 16):
+            ndq.ndq.set_multi_grid(f)
+            for L in lats:
+                L["y"].buf.zero_()
+            ndq.apply_Q_multi(jobs)
+            for L, r in zip(lats, ref):
+                assert torch.equal(L["y"].buf, r), (f, L["dims"])
+        ndq.ndq.set_multi_grid(4)
+        for L in lats:
+            L["y"].buf.zero_()
+        t = ndq.ndq.autotune_multi(jobs, reps=5)
+        assert t["factor"] in (1, 2, 3, 4, 6, 8, 12)
+        assert ndq.ndq.get_multi_grid() == t["factor"]
+        assert len(t["us"]) == 7 and all(v > 0 for v in t["us"].values())
+        assert t["us_best"] <= t["us_previous"]
+        for L, r in zip(lats, ref):
+            assert torch.equal(L["y"].buf, r), L["dims"]
+        got = lats[0]["y"].unpack().cpu().numpy()
+        L = lats[0]
+        assert rel_l2(got[0], dirac.apply_Q(L["u"], L["psi"][0], L["m"], L["dims"])) <= TOL[ndq.F32]
+    finally:
+        ndq.ndq.set_multi_grid(4)
+
+
 def test_autotune_mrhs_and_cache(tmp_path, monkeypatch):
     """The work-order autotuner of the multi-RHS stencil picks an order, records
     it for its key, appends it to the NDQ_TUNE_CACHE file, and a second call
