@@ -209,8 +209,10 @@ def solve_leg(log, sectors_fp64=False):
     log(f"solve leg: launch tuning {time.perf_counter() - t0:.1f} s: {tuned}")
     t0 = time.perf_counter()
     # a block of 20 + 40 vectors: the 20 lowest modes sit in a dense cluster, and
-    # the larger block converges in fewer filter steps (measured 36 s vs 55 s with 20 + 8)
-    modes, nu, rho, info = ndq.lowmodes_compute(g, U64, M, LAM_MAX, start, SOLVE_NEV, nextra=40, tol=1e-11)
+    # the larger block converges in fewer filter steps (measured 36 s vs 55 s with 20 + 8);
+    # the filter of the early restarts on the F32 links (FP64 Rayleigh-Ritz throughout)
+    modes, nu, rho, info = ndq.lowmodes_compute(g, U64, M, LAM_MAX, start, SOLVE_NEV, nextra=40, tol=1e-11,
+                                                U_lo=U32)
     t_modes = time.perf_counter() - t0
     log(f"solve leg: low modes {t_modes:.1f} s, {info['q_applies']} Q applies, lam_next {info['lam_next']:.5f}")
     k = (info["lam_next"] - info["rho_next"]) / LAM_MAX
@@ -221,7 +223,7 @@ def solve_leg(log, sectors_fp64=False):
     t_approx = time.perf_counter() - t0
     ov64 = ndq.Overlap(g, M, ap64, LAM_MAX, modes=modes, nu=nu, mq=SOLVE_MQ)
     ov_lo = ndq.Overlap(g, M, ap_lo, LAM_MAX, modes=modes, nu=nu, mq=SOLVE_MQ)
-    out = {"workload": "D_N^m x = b, 24^3x48, m=-1.4, mq=0.05, 20 exact low modes (FP64 block Chebyshev-filtered subspace iteration), "
+    out = {"workload": "D_N^m x = b, 24^3x48, m=-1.4, mq=0.05, 20 exact low modes (block Chebyshev-filtered subspace iteration, FP64 Rayleigh-Ritz and residues, the filter of the early restarts on F32 links), "
                        "complex Gaussian b (and a chiral point source for the inner-solver comparison), true relative "
                        "residual 1e-10 with the FP64 operator",
            "dims": list(SOLVE_DIMS), "setup_s": {"fields": round(t_fields, 2), "lowmodes": round(t_modes, 2),
@@ -229,7 +231,8 @@ def solve_leg(log, sectors_fp64=False):
            "lowmodes": {"nev": SOLVE_NEV, "nu_abs_min": float(np.abs(nu).min()), "nu_abs_max": float(np.abs(nu).max()),
                         "lam_next": info["lam_next"], "max_rho": info["max_rho"], "kappa_plus": info["kappa_plus"],
                         "kappa_minus": info["kappa_minus"], "q_applies": info["q_applies"],
-                        "restarts": info["restarts"], "cheb_degree": info["cheb_degree"], "block": SOLVE_NEV + 40},
+                        "restarts": info["restarts"], "restarts_f32_filter": info["restarts_lo"],
+                        "cheb_degree": info["cheb_degree"], "block": SOLVE_NEV + 40},
            "launch_tuning": tuned,
            "approximant": {"kind": "minimax polynomial (Clenshaw)", "eps": eps, "degree_fp64": ap64.n,
                            "delta_fp64": ap64.delta, "degree_inner": ap_lo.n, "delta_inner": ap_lo.delta}}

@@ -332,6 +332,14 @@ typedef struct {
                              modes to project in [nev_min, nev] where the relative gap
                              |nu_(l+1)| / |nu_l| to the next mode is largest (Sec. 2.3: the gap
                              should not be accidentally small); reported as nev_used          */
+    const ndq_gauge* U_lo; /* NULL, or F32 links of the same gauge field (subspace method
+                             only): the filter of the early restarts runs on F32 copies of the
+                             block with these links, the orthonormalisation, Rayleigh-Ritz and
+                             residues stay FP64; after the first restart whose largest rho_k is
+                             <= lo_until * lam_max, or three F32 restarts that did not halve the
+                             smallest such value so far, the filter is FP64.  Convergence is
+                             decided in FP64 as without U_lo.                                */
+    double lo_until;      /* switch point of U_lo (<= 0: 1e-5)                                */
 } ndq_lowmode_params;
 
 enum { NDQ_LM_SUBSPACE = 0, NDQ_LM_LANCZOS = 1, NDQ_LM_RITZ = 2 };
@@ -356,6 +364,7 @@ typedef struct {
     double seconds;
     int32_t nev_used;     /* number l of modes to project (nev unless nev_min chose fewer);
                              kappa and bounds refer to the first l modes                      */
+    int32_t restarts_lo;  /* restarts whose filter ran on U_lo (F32)                          */
 } ndq_lowmode_info;
 
 size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params* p);

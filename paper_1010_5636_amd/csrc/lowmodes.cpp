@@ -8,7 +8,15 @@
 //    of nev + nextra vectors is filtered, orthonormalised and rotated onto the
 //    Ritz vectors of Q each iteration; the cutoff a follows the block's largest
 //    Ritz value of Q^2 and the degree d the gap to the guard pair, so the filter
-//    sharpens as the block converges; degenerate eigenspaces are no obstacle;
+//    sharpens as the block converges; degenerate eigenspaces are no obstacle.
+//    Optionally the filter of the early iterations runs on F32 copies of the
+//    block with F32 links (half the bytes per stencil application): FP32
+//    rounding limits the residues such a filtered block can reach to about
+//    1e-5 relative, far below those of the first iterations; once the residues
+//    fall below a switch point, or three F32 iterations pass without halving
+//    the best of them, the filter is FP64, and the
+//    orthonormalisation, Rayleigh-Ritz step and convergence test are FP64
+//    throughout;
 //  * thick-restart Lanczos (Wu & Simon) on B = T_d(A~), a Chebyshev
 // polynomial of A = Q^2 mapped from [a, lam_max^2] onto [-1, 1]: the low end of
 // the spectrum (below the cutoff a) becomes the dominant part of B's spectrum.
@@ -43,6 +51,9 @@ struct LmCtx {
     int64_t vb;              // bytes per FP64 full spinor
     char *VA, *VB, *W, *QU, *UU;
     char* SB = nullptr;      // block of nkeep vectors: Q T_k of the block filter
+    const ndq_gauge* Ulo = nullptr;   // F32 links for the early filter restarts (or null)
+    char *XL = nullptr, *YL = nullptr, *SL = nullptr;   // F32 blocks of nkeep vectors
+    int64_t vbl = 0;         // bytes per F32 full spinor
     double* gpart = nullptr; // Gram partial tiles (matrix-core kernel)
     double* gout = nullptr;  // Gram matrix, device, up to 64 x 64 complex
     ndq_spinor X0, X1, S;
@@ -56,12 +67,13 @@ struct LmCtx {
         qcount += 1;
         return q_combo(g, U, m, in, out, Coef{c0, nullptr}, nv, v, cv, nullptr, st);
     }
-    ndq_spinor block(char* base, int nb) const { return ndq_spinor{base, NDQ_F64, NDQ_FULL, nb}; }
+    ndq_spinor block(char* base, int nb, int prec = NDQ_F64) const { return ndq_spinor{base, prec, NDQ_FULL, nb}; }
     // the same as qapply for the nb vectors of a block, in one multi-RHS launch
+    // (on the F32 links for F32 blocks)
     int qapply_block(const ndq_spinor* in, const ndq_spinor* out, double c0, int nv = 0,
                      const ndq_spinor* const* v = nullptr, const Coef* cv = nullptr) {
         qcount += in->nrhs;
-        return q_combo_block(g, U, m, in, out, Coef{c0, nullptr}, nv, v, cv, st);
+        return q_combo_block(g, in->prec == NDQ_F64 ? U : Ulo, m, in, out, Coef{c0, nullptr}, nv, v, cv, st);
     }
     int copy(const ndq_spinor* dst, const ndq_spinor* src, double c = 1.0) {
         const ndq_spinor* v[1] = {src};
@@ -126,13 +138,14 @@ int apply_filter(LmCtx& c, const ndq_spinor* v, const ndq_spinor* out, double a,
 // Y = T_d(A~) X for all nb vectors of the block X at once (the recurrence of
 // apply_filter with multi-RHS stencil launches: the links are read once per
 // step for the whole block).  T_{k+1} overwrites T_{k-1}, so the iterates
-// alternate between X and Y; X is overwritten.  Needs c.SB (nb vectors).
-int apply_filter_block(LmCtx& c, char* X, char* Y, int nb, double a, double b, int d) {
+// alternate between X and Y; X is overwritten.  S: a block of nb vectors
+// (c.SB for FP64).  prec: of X, Y and S (F32: on c.Ulo, arithmetic in FP32).
+int apply_filter_block(LmCtx& c, char* X, char* Y, char* S, int prec, int nb, double a, double b, int d) {
     const double c1 = 2.0 / (b - a), c2 = -(a + b) / (b - a);
     int rc;
-    const ndq_spinor s = c.block(c.SB, nb);
-    ndq_spinor tp = c.block(X, nb);   // T_{k-1}
-    ndq_spinor tc = c.block(Y, nb);   // T_k
+    const ndq_spinor s = c.block(S, nb, prec);
+    ndq_spinor tp = c.block(X, nb, prec);   // T_{k-1}
+    ndq_spinor tc = c.block(Y, nb, prec);   // T_k
     if ((rc = c.qapply_block(&tp, &s, 1.0))) return rc;
     {
         const ndq_spinor* vv[1] = {&tp};
@@ -146,8 +159,20 @@ int apply_filter_block(LmCtx& c, char* X, char* Y, int nb, double a, double b, i
         if ((rc = c.qapply_block(&s, &tp, 2.0 * c1, 2, vv, cv))) return rc;   // T_{k+1} into T_{k-1}'s buffer
         std::swap(tp, tc);
     }
-    if (tc.data != Y) NDQ_HIP(hipMemcpyAsync(Y, tc.data, (size_t)c.vb * nb, hipMemcpyDeviceToDevice, c.st));
+    const size_t bytes = (size_t)(prec == NDQ_F64 ? c.vb : c.vbl) * nb;
+    if (tc.data != Y) NDQ_HIP(hipMemcpyAsync(Y, tc.data, bytes, hipMemcpyDeviceToDevice, c.st));
     return NDQ_OK;
+}
+
+// The block filter of the early restarts: X (FP64) rounded to F32, filtered with
+// the F32 links in FP32 arithmetic, the result widened into Y (FP64).
+int apply_filter_block_lo(LmCtx& c, char* X, char* Y, int nb, double a, double b, int d) {
+    int rc;
+    const ndq_spinor x64 = c.block(X, nb), y64 = c.block(Y, nb);
+    const ndq_spinor xl = c.block(c.XL, nb, NDQ_F32), yl = c.block(c.YL, nb, NDQ_F32);
+    if ((rc = convert(c.g, &xl, &x64, c.st))) return rc;
+    if ((rc = apply_filter_block(c, c.XL, c.YL, c.SL, NDQ_F32, nb, a, b, d))) return rc;
+    return convert(c.g, &y64, &yl, c.st);
 }
 
 // Lanczos steps j = j0 .. m-1 on the basis block `base` (m+1 vectors), recording
@@ -445,6 +470,10 @@ size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params*
     ar.take(vb * (p->nev + 1));     // QU
     ar.take(vb * (p->nev + 1));     // UU
     if (p->method == NDQ_LM_SUBSPACE) ar.take(vb * nkeep);   // SB
+    if (p->method == NDQ_LM_SUBSPACE && p->U_lo) {
+        const size_t vbl = (size_t)spinor_rhs_bytes(g, NDQ_F32, NDQ_FULL);
+        for (int i = 0; i < 3; ++i) ar.take(vbl * nkeep);    // XL, YL, SL
+    }
     for (int i = 0; i < 3; ++i) ar.take(vb);
     ar.take(partials_capacity(g, 2 * NDQ_MAX_MODES));
     ar.take(2 * NDQ_MAX_MODES * sizeof(double));
@@ -470,6 +499,11 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     if (p->method != NDQ_LM_SUBSPACE && !lanczos && !ritz)
         return fail(NDQ_EINVAL, "low modes: unknown method %d", p->method);
     if (p->nev_min < 0 || p->nev_min > p->nev) return fail(NDQ_EINVAL, "low modes: nev_min must be in [0, nev]");
+    if (p->U_lo) {
+        if (p->method != NDQ_LM_SUBSPACE) return fail(NDQ_EINVAL, "low modes: U_lo needs the subspace method");
+        if ((rc = check_gauge(p->U_lo))) return rc;
+        if (p->U_lo->prec != NDQ_F32) return fail(NDQ_EPREC, "low modes: U_lo must hold F32 links");
+    }
     const int nev = p->nev, nkeep = nev + std::max(p->nextra, 1);
     const int mb = lanczos ? p->basis : nkeep;
     if (nev < 1 || nkeep > NDQ_MAX_MODES || (lanczos && (mb > NDQ_MAX_MODES - 1 || mb < nkeep + 2)))
@@ -490,6 +524,13 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
     c.QU = static_cast<char*>(ar.take(c.vb * (nev + 1)));
     c.UU = static_cast<char*>(ar.take(c.vb * (nev + 1)));
     if (p->method == NDQ_LM_SUBSPACE) c.SB = static_cast<char*>(ar.take(c.vb * nkeep));
+    if (p->method == NDQ_LM_SUBSPACE && p->U_lo) {
+        c.Ulo = p->U_lo;
+        c.vbl = spinor_rhs_bytes(g, NDQ_F32, NDQ_FULL);
+        c.XL = static_cast<char*>(ar.take(c.vbl * nkeep));
+        c.YL = static_cast<char*>(ar.take(c.vbl * nkeep));
+        c.SL = static_cast<char*>(ar.take(c.vbl * nkeep));
+    }
     c.X0 = ws_spinor(ar, g, NDQ_F64);
     c.X1 = ws_spinor(ar, g, NDQ_F64);
     c.S = ws_spinor(ar, g, NDQ_F64);
@@ -513,7 +554,7 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
 
     double a = p->cheb_lo;
     int d = p->cheb_degree;
-    int restarts = 0;
+    int restarts = 0, restarts_lo = 0;
     bool converged = false;
     RRResult rr;
     char* X = c.VA;
@@ -576,8 +617,16 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
         }
         const bool fixed_d = d > 0;
         if (!fixed_d) d = filter_degree(a, b, 0.5 * a);
+        // F32 filter while the residues are far above what FP32 resolves
+        bool lo = c.Ulo != nullptr;
+        const double lo_until = (p->lo_until > 0 ? p->lo_until : 1e-5) * lam_max;
+        double best_lo = HUGE_VAL;
+        int stall = 0;
         for (;;) {
-            if ((rc = apply_filter_block(c, X, XS, nkeep, a, b, d))) return rc;
+            if (lo) rc = apply_filter_block_lo(c, X, XS, nkeep, a, b, d);
+            else rc = apply_filter_block(c, X, XS, c.SB, NDQ_F64, nkeep, a, b, d);
+            if (rc) return rc;
+            restarts_lo += lo ? 1 : 0;
             std::swap(X, XS);
             if ((rc = orthonormalise(c, X, nkeep))) return rc;
             if ((rc = rayleigh_ritz_q(c, X, W, XS, WS, nkeep, nsel, true, rr))) return rc;
@@ -587,6 +636,17 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
             if (max_rho <= tol * lam_max && rr.guard_res <= guard_tol * b) {
                 converged = true;
                 break;
+            }
+            if (lo) {
+                // FP64 from here once the residues are small, or after three F32
+                // restarts without halving the best residue so far
+                if (max_rho < 0.5 * best_lo) {
+                    best_lo = max_rho;
+                    stall = 0;
+                } else {
+                    ++stall;
+                }
+                if (max_rho <= lo_until || stall >= 3) lo = false;
             }
             if (restarts >= max_restarts) break;
             // sharpen the filter: cutoff at the block's largest Rayleigh quotient of A
@@ -710,6 +770,7 @@ int ndq_lowmodes_compute(const ndq_geom* g, const ndq_gauge* U, double m, double
         info->cheb_lo = a;
         info->cheb_degree = d;
         info->restarts = restarts;
+        info->restarts_lo = restarts_lo;
         info->q_applies = c.qcount;
         info->max_rho = max_rho;
         info->rho_next = rho_next;

@@ -92,7 +92,8 @@ class _Stats(ctypes.Structure):
 class _LmParams(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int32), ("nextra", ctypes.c_int32), ("basis", ctypes.c_int32),
                 ("cheb_degree", ctypes.c_int32), ("cheb_lo", ctypes.c_double), ("tol", ctypes.c_double),
-                ("max_restarts", ctypes.c_int32), ("method", ctypes.c_int32), ("nev_min", ctypes.c_int32)]
+                ("max_restarts", ctypes.c_int32), ("method", ctypes.c_int32), ("nev_min", ctypes.c_int32),
+                ("U_lo", ctypes.c_void_p), ("lo_until", ctypes.c_double)]
 
 
 class _LmInfo(ctypes.Structure):
@@ -100,7 +101,7 @@ class _LmInfo(ctypes.Structure):
                 ("bound_plus", ctypes.c_double), ("bound_minus", ctypes.c_double), ("cheb_lo", ctypes.c_double),
                 ("cheb_degree", ctypes.c_int32), ("restarts", ctypes.c_int32), ("q_applies", ctypes.c_int64),
                 ("max_rho", ctypes.c_double), ("rho_next", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("nev_used", ctypes.c_int32)]
+                ("nev_used", ctypes.c_int32), ("restarts_lo", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -588,11 +589,15 @@ def noalloc_scratch_bytes() -> int:
 
 def lowmodes_compute(geom: Geometry, U: GaugeField, m: float, lam_max: float, start: SpinorField, nev: int,
                      nextra: int = 8, basis: int = 0, cheb_degree: int = 0, cheb_lo: float = 0.0, tol: float = 1e-10,
-                     max_restarts: int = 0, method: int = 0, nev_min: int = 0, stream=None):
-    """Low modes of Q: returns (modes SpinorField (F64, FULL, nrhs=nev), nu, rho, info dict)."""
+                     max_restarts: int = 0, method: int = 0, nev_min: int = 0, U_lo: "GaugeField" = None,
+                     lo_until: float = 0.0, stream=None):
+    """Low modes of Q: returns (modes SpinorField (F64, FULL, nrhs=nev), nu, rho, info dict).
+    U_lo: F32 links of the same field for the filter of the early restarts (subspace method)."""
     import numpy as np
     basis = basis or min(63, nev + nextra + max(12, nev))
-    p = _LmParams(nev, nextra, basis, cheb_degree, cheb_lo, tol, max_restarts, method, nev_min)
+    p = _LmParams(nev, nextra, basis, cheb_degree, cheb_lo, tol, max_restarts, method, nev_min,
+                  ctypes.cast(ctypes.pointer(U_lo.desc), ctypes.c_void_p) if U_lo is not None else None,
+                  float(lo_until))
     nbytes = int(lib().ndq_lowmodes_workspace_bytes(geom.handle, ctypes.byref(p)))
     if nbytes == 0:
         raise NdqError(-1, "bad low-mode parameters")

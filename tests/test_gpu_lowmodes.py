@@ -7,6 +7,8 @@
 * 8^4 random links, l = 12: residues recomputed by the oracle's stencil.
 * 4^4 free field, l = 48 (block method): the exactly 48-fold degenerate
   |lambda| = 0.6 eigenspace, projector against the exact one.
+* the block method with an F32 filter phase (4^4 against the dense spectrum, 8^4
+  against the FP64-only run and the oracle's residues).
 * every run: the library's kappa_+-, Eq. 10 bounds (Eq. 9, Eq. 10) against the
   oracle's gap_distances / kappas / projector_bound evaluated on the library's
   own nu, rho and certified lower gap lam_next - rho_next (relative 1e-10).
@@ -125,6 +127,50 @@ def test_lowmodes_8c4_residuals(method):
     assert np.all(np.abs(nu) <= info["lam_next"] + 1e-12)
     assert np.all(np.diff(np.abs(nu)) >= -1e-14)
     check_diagnostics(nu, rho, info)
+
+
+@pytest.mark.parametrize("dims,nev,seed", [((4, 4, 4, 4), 8, None), ((8, 8, 8, 8), 12, 5)])
+def test_lowmodes_f32_filter_phase(dense4, dims, nev, seed):
+    """The subspace method with F32 links for the early filter restarts reaches the
+    same FP64 modes: eigenvalues against the dense spectrum (4^4) or the FP64-only
+    run (8^4), residues recomputed by the oracle's stencil, orthonormality."""
+    u = dense4["u"] if seed is None else synthetic.gauge_field(dims, seed=seed)
+    g = ndq.Geometry(dims)
+    U = ndq.GaugeField.pack(g, cu(u), ndq.F64, 18)
+    U32 = ndq.GaugeField.pack(g, cu(u), ndq.F32, 12)
+    v = geometry.volume(dims)
+    start = ndq.SpinorField.pack(g, cu(synthetic.start_vector(v)), ndq.F64, ndq.FULL)
+    tol = 1e-11 if seed is None else 1e-10
+    modes, nu, rho, info = ndq.lowmodes_compute(g, U, M, LMAX, start, nev, nextra=8, tol=tol, U_lo=U32)
+    assert info["restarts_lo"] >= 1 and info["restarts"] > info["restarts_lo"], info
+    if seed is None:
+        lam = dense4["eig"][0][dense4["order"]]
+        ref = np.sort(lam[:nev])
+    else:
+        _, _, _, nu64, _, _ = run(dims, u, nev, tol=tol)
+        ref = np.sort(nu64)
+    assert np.allclose(np.sort(nu), ref, atol=1e-9), (nu, ref)
+    um = modes.unpack().cpu().numpy()
+    qu = dirac.apply_Q(u, um, M, dims).reshape(nev, -1)
+    rho_o = np.linalg.norm(qu - nu[:, None] * um.reshape(nev, -1), axis=1)
+    assert np.all(rho_o <= tol * LMAX * 1.01)
+    gram = um.reshape(nev, -1).conj() @ um.reshape(nev, -1).T
+    assert np.abs(gram - np.eye(nev)).max() < 1e-12
+    check_diagnostics(nu, rho, info)
+
+
+def test_lowmodes_f32_filter_rejects_bad_links():
+    """U_lo must be F32 links and needs the subspace method."""
+    dims = (4, 4, 4, 4)
+    u = synthetic.gauge_field(dims)
+    g = ndq.Geometry(dims)
+    U = ndq.GaugeField.pack(g, cu(u), ndq.F64, 18)
+    start = ndq.SpinorField.pack(g, cu(synthetic.start_vector(256)), ndq.F64, ndq.FULL)
+    with pytest.raises(ndq.NdqError):
+        ndq.lowmodes_compute(g, U, M, LMAX, start, 4, U_lo=U)
+    U32 = ndq.GaugeField.pack(g, cu(u), ndq.F32, 12)
+    with pytest.raises(ndq.NdqError):
+        ndq.lowmodes_compute(g, U, M, LMAX, start, 4, U_lo=U32, method=ndq.ndq.LM_LANCZOS)
 
 
 def test_lowmodes_free_field_degenerate():
