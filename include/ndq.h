@@ -376,6 +376,9 @@ size_t ndq_lowmodes_workspace_bytes(const ndq_geom* g, const ndq_lowmode_params*
  * (Eq. 8) and kappa_+- (Eq. 9), bound (Eq. 10).  Ritz pairs are ordered by
  * |Q u|^2, the Rayleigh quotient of Q^2 (equal to nu^2 once converged), which
  * keeps spurious near-zero Ritz values of the indefinite Q out of the result.
+ * With p->U_lo (subspace method) the filter of the early iterations runs in
+ * FP32 on F32 copies of the block (see ndq_lowmode_params); the returned modes
+ * and residues are FP64 as without it.
  *   U: F64 links;  start: F64 NDQ_FULL spinor (nonzero);  d_modes: out, nev packed F64
  *   NDQ_FULL spinors back to back (orthonormal);  nu, rho: host arrays of nev, in
  *   that order (|nu| ascending once converged).  Converged means every rho_k <=
