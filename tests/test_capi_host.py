@@ -86,6 +86,17 @@ def test_multi_grid_validation(ndq):
         ndq.set_multi_grid(4)
 
 
+def test_multi_grid_autotune_validation(ndq):
+    """The grid autotuner checks its jobs before any launch (no stream is touched)."""
+    import types
+    null_stream = types.SimpleNamespace(cuda_stream=0)
+    with pytest.raises(ndq.NdqError):
+        ndq.autotune_multi([], stream=null_stream)
+    with pytest.raises(ndq.NdqError):
+        ndq.autotune_multi([], reps=0, stream=null_stream)
+    assert ndq.get_multi_grid() == 4
+
+
 def test_descriptor_validation_before_launch(ndq):
     """Bad descriptors fail on the host (no device memory is touched)."""
     lib = ndq.lib()
