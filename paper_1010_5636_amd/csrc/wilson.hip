@@ -125,7 +125,9 @@ __device__ __forceinline__ void hop_bwd(const C<R> s[12], const C<R> u[3][3], C<
     }
 }
 
-template <int SP, int LP, int RECON, int MU, bool NT>
+// PAIR64: FP64 also issues both hops' loads together (the direction split with
+// 12- or 8-real links, where the registers this takes keep 3 wavefronts per SIMD).
+template <int SP, int LP, int RECON, int MU, bool NT, bool PAIR64 = false>
 __device__ __forceinline__ void hop_pair(const WilsonArgs& a, int p, int32_t i, const int32_t nb[8],
                                          const SpinorView& vin, C<typename SpinorIO<SP>::R> acc[12]) {
     using R = typename SpinorIO<SP>::R;
@@ -133,9 +135,9 @@ __device__ __forceinline__ void hop_pair(const WilsonArgs& a, int p, int32_t i, 
     C<R> sf[12], sb[12];
     uint32_t wf[F::kWords], wb[F::kWords];
     C<typename LinkReal<LP>::R> u[3][3];
-    if constexpr (SP != P64) {
+    if constexpr (SP != P64 || PAIR64) {
         // all loads of both hops first: one memory round trip instead of two
-        // (FP64 keeps the two trips: its registers would halve the occupancy)
+        // (FP64 otherwise keeps the two trips: its registers would cut the occupancy)
         SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[MU], sf);
         link_load_words<LP, RECON, NT>(a.links, a.g.vh, p * 4 + MU, i, wf);
         SpinorIO<SP>::load(vin, (int64_t)vin.site0 + nb[4 + MU], sb);
@@ -297,10 +299,10 @@ __global__ void __launch_bounds__(256) k_wilson_dirsplit(WilsonArgs a) {
         for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
         const SpinorView& vin = a.in[y];
         switch (w) {
-            case 0: hop_pair<SP, LP, RECON, 0, NT>(a, p, i, nb, vin, acc); break;
-            case 1: hop_pair<SP, LP, RECON, 1, NT>(a, p, i, nb, vin, acc); break;
-            case 2: hop_pair<SP, LP, RECON, 2, NT>(a, p, i, nb, vin, acc); break;
-            default: hop_pair<SP, LP, RECON, 3, NT>(a, p, i, nb, vin, acc); break;
+            case 0: hop_pair<SP, LP, RECON, 0, NT, RECON != 18>(a, p, i, nb, vin, acc); break;
+            case 1: hop_pair<SP, LP, RECON, 1, NT, RECON != 18>(a, p, i, nb, vin, acc); break;
+            case 2: hop_pair<SP, LP, RECON, 2, NT, RECON != 18>(a, p, i, nb, vin, acc); break;
+            default: hop_pair<SP, LP, RECON, 3, NT, RECON != 18>(a, p, i, nb, vin, acc); break;
         }
 #pragma unroll
         for (int k = 0; k < 12; ++k) part[w][k][lane] = acc[k];
